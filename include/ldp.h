@@ -1,0 +1,168 @@
+/*
+ * ldp.h -- C ABI of the MI355X (gfx950) Local Directional Pattern library.
+ *
+ * Method: "An Acceleration Scheme to The Local Directional Pattern"
+ * (Ayami and Shabat, arXiv 1810.11518).  For every interior pixel of an
+ * 8-bit grayscale image the library computes the eight Kirsch directional
+ * responses (Section 2.2.1, Eq. 1) through shared neighbour sums (the
+ * redundancy-omitting scheme of Section 2.3, Eqs. 7-29), selects the k-th
+ * largest response and forms the 8-bit LDP code (Section 2.2.2, Eqs. 2-3),
+ * and counts codes in per-cell histograms (Section 2.2.3, Eqs. 4-5).
+ *
+ * Conventions (fixed by the library; see the design notes):
+ *   - x is the row, y the column; M0..M7 are the Kirsch compass masks
+ *     East, North-East, North, North-West, West, South-West, South,
+ *     South-East, applied as a correlation (Eq. 1);
+ *   - responses are signed; m_k is the k-th element of the eight responses
+ *     in descending order with duplicates kept; bit i of the code is set when
+ *     m_i >= m_k (Eq. 3), so ties can set more than k bits;
+ *   - only interior pixels (1 <= x <= H-2, 1 <= y <= W-2) get a code; the
+ *     code map is dense, (H-2) rows of (W-2) bytes:
+ *         codes[(x-1)*(W-2) + (y-1)];
+ *   - histograms have 256 uint32 bins per cell, indexed by the raw code, for a
+ *     cells_y x cells_x grid laid over the code map with a floor partition
+ *     (code row r is in cell row r*cells_y/(H-2), code column c in cell column
+ *     c*cells_x/(W-2)); layout hist[(cy*cells_x + cx)*256 + code]; every call
+ *     overwrites the whole histogram array.
+ *
+ * Memory: every pointer argument except the descriptor arrays of the batch
+ * calls is DEVICE memory owned by the caller; the library never frees it.
+ * Images may have any alignment and any row pitch ("stride", bytes, >= W).
+ *
+ * Streams and errors: calls enqueue work on `stream` (0 = the null stream)
+ * and return at once.  Argument errors are detected on the host before
+ * anything is launched and return LDP_ERR_INVALID_ARG; a failed launch
+ * returns LDP_ERR_HIP.  Faults during execution surface at the caller's next
+ * synchronisation of the stream.  Nothing is thrown across this boundary.
+ * Calls on different streams may run concurrently; the kernels keep no state.
+ */
+#ifndef LDP_H
+#define LDP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t *ldp_stream_t; /* the same type as hipStream_t */
+
+enum {
+    LDP_OK = 0,
+    LDP_ERR_INVALID_ARG = -1,
+    LDP_ERR_HIP = -2,
+    LDP_ERR_NO_MEMORY = -3,
+    LDP_ERR_UNSUPPORTED = -4,
+    LDP_ERR_BUSY = -5
+};
+
+/* Largest image side the kernels accept (rows and columns). */
+#define LDP_MAX_SIDE 65536
+
+/* Human-readable text for a status code (static storage). */
+const char *ldp_status_string(int status);
+
+/* Library ABI version, currently 1. */
+int ldp_version(void);
+
+/*
+ * ldp_codes -- LDP code of every interior pixel (Eqs. 1-3).
+ *   img     device, H rows of W bytes, row pitch `stride` bytes (>= W).
+ *   H, W    image rows and columns, 3 <= H, W <= LDP_MAX_SIDE.
+ *   k       number of most outstanding responses, 1..8 (the paper uses 3).
+ *   codes   device, (H-2)*(W-2) bytes, written densely as described above.
+ * Errors: LDP_ERR_INVALID_ARG for a null pointer, H or W out of range,
+ * stride < W or k outside 1..8.
+ */
+int ldp_codes(const uint8_t *img, int32_t H, int32_t W, int64_t stride, int32_t k,
+              uint8_t *codes, ldp_stream_t stream);
+
+/*
+ * ldp_histograms -- per-cell 256-bin histograms of a code map (Eqs. 4-5).
+ *   codes   device, the dense (H-2)x(W-2) code map of an H x W image.
+ *   H, W    the IMAGE dimensions (3..LDP_MAX_SIDE).
+ *   cells_y, cells_x  grid, 1 <= cells_y <= H-2, 1 <= cells_x <= W-2.
+ *   hist    device, cells_y*cells_x*256 uint32, overwritten.
+ * Errors: LDP_ERR_INVALID_ARG for a null pointer or sizes out of range.
+ */
+int ldp_histograms(const uint8_t *codes, int32_t H, int32_t W, int32_t cells_y,
+                   int32_t cells_x, uint32_t *hist, ldp_stream_t stream);
+
+/*
+ * ldp_extract -- codes and histograms of one image in a single launch
+ * (Eqs. 1-5): the same results as ldp_codes followed by ldp_histograms,
+ * without reading the code map back.  Arguments as above; `codes` may be
+ * NULL when only the histograms are wanted.
+ */
+int ldp_extract(const uint8_t *img, int32_t H, int32_t W, int64_t stride, int32_t k,
+                int32_t cells_y, int32_t cells_x, uint8_t *codes, uint32_t *hist,
+                ldp_stream_t stream);
+
+/* ---------------------------------------------------------------- batches
+ *
+ * Many images of any sizes in ONE persistent launch: the work (row bands of
+ * every image, split so that histogram cells are owned by one workgroup) is
+ * laid out in a device table, workgroups pull work items from a device queue,
+ * and the launch is captured once in a HIP graph and replayed.  Each image's
+ * codes and histograms are exactly those of ldp_extract on that image.
+ */
+typedef struct ldp_image_desc {
+    const uint8_t *img; /* device, H x W, pitch `stride` */
+    uint8_t *codes;     /* device, (H-2)*(W-2) bytes, or NULL for histograms only */
+    uint32_t *hist;     /* device, cells_y*cells_x*256 uint32 */
+    int64_t stride;     /* bytes between rows, >= W */
+    int32_t H, W;       /* 3..LDP_MAX_SIDE */
+} ldp_image_desc;
+
+/* Launch shape of the batched kernel (chosen by the autotuner; zero fields
+ * take defaults). */
+typedef struct ldp_tune {
+    int32_t cell_rows_per_item; /* cell rows of one image per work item, >= 1 */
+    int32_t block_threads;      /* threads per workgroup: 256, 512 or 1024 */
+    int32_t grid_blocks;        /* persistent workgroups; 0 = fill the device */
+    int32_t rows_per_task;      /* target code rows per lane task, >= 1 */
+} ldp_tune;
+
+typedef struct ldp_batch_plan ldp_batch_plan;
+
+/*
+ * ldp_batch_plan_create -- a plan for up to max_images images and up to
+ * max_pixels total pixels, for fixed k and cell grid.  Allocates the plan's
+ * device work table and queue (owned by the plan, released by destroy).
+ * `tune` may be NULL.  Errors: LDP_ERR_INVALID_ARG, LDP_ERR_NO_MEMORY.
+ */
+int ldp_batch_plan_create(ldp_batch_plan **plan, int32_t max_images, int64_t max_pixels,
+                          int32_t k, int32_t cells_y, int32_t cells_x, const ldp_tune *tune);
+
+/*
+ * ldp_batch_plan_set -- (re)load the batch: `descs` is a HOST array of n
+ * descriptors (copied; the caller may reuse it on return).  Builds the work
+ * table on the host and uploads it on `stream`.  The captured graph is
+ * reused when only the descriptors change.  Every image must satisfy the
+ * ldp_extract argument rules and have at least cells_y+2 rows and cells_x+2
+ * columns.  Errors: LDP_ERR_INVALID_ARG (the offending image is not
+ * launched; nothing is), LDP_ERR_NO_MEMORY if n or the pixel total exceed
+ * the plan's capacity.
+ */
+int ldp_batch_plan_set(ldp_batch_plan *plan, const ldp_image_desc *descs, int32_t n,
+                       ldp_stream_t stream);
+
+/* ldp_batch_run -- run the loaded batch on `stream` (one graph launch). */
+int ldp_batch_run(ldp_batch_plan *plan, ldp_stream_t stream);
+
+/* ldp_batch_run_per_image -- the same batch as one ldp_extract launch per
+ * image, for comparison with the persistent launch. */
+int ldp_batch_run_per_image(ldp_batch_plan *plan, ldp_stream_t stream);
+
+/* ldp_batch_plan_info -- work items and persistent workgroups of the loaded
+ * batch (either pointer may be NULL). */
+int ldp_batch_plan_info(const ldp_batch_plan *plan, int64_t *work_items, int32_t *grid_blocks);
+
+/* ldp_batch_plan_destroy -- release the plan (waits for its device work). */
+int ldp_batch_plan_destroy(ldp_batch_plan *plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LDP_H */

@@ -1,0 +1,215 @@
+"""Thin ctypes binding of libldp.so (include/ldp.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of libldp.so.  Tensors are torch CUDA (ROCm) tensors; torch supplies
+device memory and the current stream.  If the library is not built this
+module raises -- there is no fallback path.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libldp.so")
+
+LDP_OK = 0
+LDP_ERR_INVALID_ARG = -1
+LDP_ERR_HIP = -2
+LDP_ERR_NO_MEMORY = -3
+LDP_ERR_UNSUPPORTED = -4
+LDP_ERR_BUSY = -5
+
+# every symbol include/ldp.h declares
+EXPORTED = [
+    "ldp_status_string", "ldp_version", "ldp_codes", "ldp_histograms", "ldp_extract",
+    "ldp_batch_plan_create", "ldp_batch_plan_set", "ldp_batch_run", "ldp_batch_run_per_image",
+    "ldp_batch_plan_info", "ldp_batch_plan_destroy",
+    "ldp_server_create", "ldp_server_submit", "ldp_server_poll", "ldp_server_stats",
+    "ldp_server_destroy",
+]
+
+
+class LdpError(RuntimeError):
+    def __init__(self, status, what=""):
+        self.status = status
+        super().__init__("%s: %s (status %d)" % (what, status_string(status), status))
+
+
+class ImageDesc(ctypes.Structure):
+    _fields_ = [("img", ctypes.c_void_p), ("codes", ctypes.c_void_p), ("hist", ctypes.c_void_p),
+                ("stride", ctypes.c_int64), ("H", ctypes.c_int32), ("W", ctypes.c_int32)]
+
+
+class Tune(ctypes.Structure):
+    _fields_ = [("cell_rows_per_item", ctypes.c_int32), ("block_threads", ctypes.c_int32),
+                ("grid_blocks", ctypes.c_int32), ("rows_per_task", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load():
+    """Load libldp.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libldp.so is not built (%s); run __graft_entry__.build() or "
+                           "python -m paper_1810_11518_amd.build" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    p, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    sig = {
+        "ldp_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+        "ldp_version": (ctypes.c_int, []),
+        "ldp_codes": (ctypes.c_int, [p, i32, i32, i64, i32, p, p]),
+        "ldp_histograms": (ctypes.c_int, [p, i32, i32, i32, i32, p, p]),
+        "ldp_extract": (ctypes.c_int, [p, i32, i32, i64, i32, i32, i32, p, p, p]),
+        "ldp_batch_plan_create": (ctypes.c_int, [ctypes.POINTER(p), i32, i64, i32, i32, i32,
+                                                 ctypes.POINTER(Tune)]),
+        "ldp_batch_plan_set": (ctypes.c_int, [p, ctypes.POINTER(ImageDesc), i32, p]),
+        "ldp_batch_run": (ctypes.c_int, [p, p]),
+        "ldp_batch_run_per_image": (ctypes.c_int, [p, p]),
+        "ldp_batch_plan_info": (ctypes.c_int, [p, ctypes.POINTER(i64), ctypes.POINTER(i32)]),
+        "ldp_batch_plan_destroy": (ctypes.c_int, [p]),
+    }
+    for name, (res, args) in sig.items():
+        if not hasattr(lib, name):
+            continue
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def status_string(status):
+    try:
+        return load().ldp_status_string(status).decode()
+    except RuntimeError:
+        return "status %d" % status
+
+
+def _check(status, what):
+    if status != LDP_OK:
+        raise LdpError(status, what)
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _image_args(img):
+    import torch
+    if not isinstance(img, torch.Tensor) or img.dtype != torch.uint8 or img.dim() != 2:
+        raise ValueError("image must be a 2-D torch.uint8 tensor")
+    if not img.is_cuda:
+        raise ValueError("image must be a device tensor")
+    if img.stride(1) != 1:
+        raise ValueError("image columns must be contiguous (stride(1) == 1)")
+    H, W = img.shape
+    return img.data_ptr(), int(H), int(W), int(img.stride(0))
+
+
+def codes(img, k=3, out=None, stream=None):
+    """LDP codes of every interior pixel: uint8 tensor (H-2, W-2)."""
+    import torch
+    ptr, H, W, stride = _image_args(img)
+    if out is None:
+        out = torch.empty((max(H - 2, 0), max(W - 2, 0)), dtype=torch.uint8, device=img.device)
+    _check(load().ldp_codes(ptr, H, W, stride, k, out.data_ptr(), _stream(stream)), "ldp_codes")
+    return out
+
+
+def histograms(code_map, cells_y, cells_x, out=None, stream=None):
+    """Per-cell 256-bin histograms of a dense code map: int32 tensor
+    (cells_y, cells_x, 256) holding the uint32 counts."""
+    import torch
+    if code_map.dtype != torch.uint8 or code_map.dim() != 2 or not code_map.is_contiguous():
+        raise ValueError("code map must be a contiguous 2-D torch.uint8 tensor")
+    Hc, Wc = code_map.shape
+    if out is None:
+        out = torch.empty((cells_y, cells_x, 256), dtype=torch.int32, device=code_map.device)
+    _check(load().ldp_histograms(code_map.data_ptr(), Hc + 2, Wc + 2, cells_y, cells_x,
+                                 out.data_ptr(), _stream(stream)), "ldp_histograms")
+    return out
+
+
+def extract(img, k, cells_y, cells_x, want_codes=True, codes_out=None, hist_out=None,
+            stream=None):
+    """Codes and per-cell histograms in one launch: (codes or None, hist)."""
+    import torch
+    ptr, H, W, stride = _image_args(img)
+    if want_codes and codes_out is None:
+        codes_out = torch.empty((H - 2, W - 2), dtype=torch.uint8, device=img.device)
+    if hist_out is None:
+        hist_out = torch.empty((cells_y, cells_x, 256), dtype=torch.int32, device=img.device)
+    cptr = codes_out.data_ptr() if want_codes else None
+    _check(load().ldp_extract(ptr, H, W, stride, k, cells_y, cells_x, cptr,
+                              hist_out.data_ptr(), _stream(stream)), "ldp_extract")
+    return (codes_out if want_codes else None), hist_out
+
+
+class BatchPlan:
+    """A persistent, graph-captured launch over many images (ldp_batch_*)."""
+
+    def __init__(self, max_images, max_pixels, k, cells_y, cells_x, tune=None):
+        self._lib = load()
+        self._plan = ctypes.c_void_p()
+        t = None
+        if tune is not None:
+            t = Tune(*[int(tune.get(f, 0)) for f in ("cell_rows_per_item", "block_threads",
+                                                       "grid_blocks", "rows_per_task")])
+        _check(self._lib.ldp_batch_plan_create(ctypes.byref(self._plan), max_images, max_pixels,
+                                               k, cells_y, cells_x,
+                                               ctypes.byref(t) if t is not None else None),
+               "ldp_batch_plan_create")
+        self.k, self.cells = k, (cells_y, cells_x)
+
+    @staticmethod
+    def descs(imgs, codes, hists, strides=None, Hs=None, Ws=None):
+        """Descriptor array from lists of pointers (ints) and sizes."""
+        n = len(imgs)
+        arr = (ImageDesc * n)()
+        for j in range(n):
+            arr[j].img = imgs[j]
+            arr[j].codes = codes[j] if codes is not None else None
+            arr[j].hist = hists[j]
+            arr[j].stride = strides[j]
+            arr[j].H = Hs[j]
+            arr[j].W = Ws[j]
+        return arr
+
+    def set(self, descs, stream=None):
+        _check(self._lib.ldp_batch_plan_set(self._plan, descs, len(descs), _stream(stream)),
+               "ldp_batch_plan_set")
+
+    def run(self, stream=None):
+        _check(self._lib.ldp_batch_run(self._plan, _stream(stream)), "ldp_batch_run")
+
+    def run_per_image(self, stream=None):
+        _check(self._lib.ldp_batch_run_per_image(self._plan, _stream(stream)),
+               "ldp_batch_run_per_image")
+
+    def info(self):
+        items, grid = ctypes.c_int64(), ctypes.c_int32()
+        _check(self._lib.ldp_batch_plan_info(self._plan, ctypes.byref(items), ctypes.byref(grid)),
+               "ldp_batch_plan_info")
+        return int(items.value), int(grid.value)
+
+    def close(self):
+        if self._plan:
+            self._lib.ldp_batch_plan_destroy(self._plan)
+            self._plan = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def pointer_array(values):
+    return np.asarray(values, dtype=np.uint64)

@@ -1,0 +1,304 @@
+// ldp_batch.hip -- many images of any sizes in one persistent launch.
+//
+// The host cuts every image into work items of whole cell rows, so each
+// item's histogram cells belong to exactly one workgroup and are written with
+// plain stores (no atomics, no zeroing pass).  Items are sorted largest
+// first and pulled by the resident workgroups from a device queue counter.
+// The launch (a one-thread kernel that clears the counter, then the
+// persistent kernel) is captured once in a HIP graph when the plan is made;
+// the kernels read the item count and tables from device memory, so loading
+// a new batch never re-captures the graph.
+#include <algorithm>
+#include <new>
+#include <numeric>
+#include <vector>
+
+#include "ldp_engine.hpp"
+#include "ldp_host.hpp"
+
+namespace ldp {
+
+struct Item {
+    int32_t img;        // index into the descriptor table
+    int16_t cy0, cy1;   // cell rows [cy0, cy1)
+};
+
+__global__ void clear_counter_kernel(uint32_t *meta) { meta[1] = 0; }
+
+template <int K>
+__global__ void __launch_bounds__(1024) batch_kernel(const ldp_image_desc *__restrict__ descs,
+                                                     const Item *__restrict__ items,
+                                                     uint32_t *meta, int32_t cells_y,
+                                                     int32_t cells_x, int32_t min_task_rows)
+{
+    extern __shared__ uint32_t lds[];
+    __shared__ uint32_t s_item;
+    const uint32_t n_items = meta[0];
+    for (;;) {
+        if (threadIdx.x == 0)
+            s_item = atomicAdd(&meta[1], 1u);
+        __syncthreads();
+        const uint32_t it = s_item;
+        __syncthreads();
+        if (it >= n_items)
+            break;
+        const Item w = items[it];
+        const ldp_image_desc d = descs[w.img];
+        ImgView im = make_view(d.img, d.stride, d.H, d.W, d.codes);
+        const int32_t r0 = cell_start(w.cy0, im.Hc, cells_y);
+        const int32_t r1 = cell_start(w.cy1, im.Hc, cells_y);
+        if (image_aligned_dev(d.img, d.stride))
+            fused_item<K, true>(im, lds, cells_y, cells_x, w.cy0, w.cy1, r0, r1, d.hist, false,
+                                min_task_rows);
+        else
+            fused_item<K, false>(im, lds, cells_y, cells_x, w.cy0, w.cy1, r0, r1, d.hist, false,
+                                 min_task_rows);
+    }
+}
+
+typedef void (*batch_fn)(const ldp_image_desc *, const Item *, uint32_t *, int32_t, int32_t,
+                         int32_t);
+
+static batch_fn batch_kernel_for(int k)
+{
+    switch (k) {
+    case 1: return batch_kernel<1>;
+    case 2: return batch_kernel<2>;
+    case 3: return batch_kernel<3>;
+    case 4: return batch_kernel<4>;
+    case 5: return batch_kernel<5>;
+    case 6: return batch_kernel<6>;
+    case 7: return batch_kernel<7>;
+    case 8: return batch_kernel<8>;
+    }
+    return nullptr;
+}
+
+}  // namespace ldp
+
+struct ldp_batch_plan {
+    int32_t k = 3, cells_y = 1, cells_x = 1, max_images = 0;
+    int64_t max_pixels = 0, max_items = 0;
+    int32_t threads = 512, cpi = 1, min_task_rows = 4, grid = 0;
+    size_t lds_bytes = 0;
+    int device = 0;
+    ldp_image_desc *d_descs = nullptr;
+    ldp::Item *d_items = nullptr;
+    uint32_t *d_meta = nullptr;  // [0] item count, [1] queue counter
+    ldp_image_desc *h_descs = nullptr;  // pinned staging
+    ldp::Item *h_items = nullptr;       // pinned staging
+    uint32_t *h_meta = nullptr;         // pinned staging
+    std::vector<ldp_image_desc> descs;  // the loaded batch
+    int64_t n_items = 0;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t uploaded = nullptr;
+};
+
+namespace {
+
+void release(ldp_batch_plan *p)
+{
+    if (!p)
+        return;
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+    if (p->uploaded) (void)hipEventDestroy(p->uploaded);
+    if (p->d_descs) (void)hipFree(p->d_descs);
+    if (p->d_items) (void)hipFree(p->d_items);
+    if (p->d_meta) (void)hipFree(p->d_meta);
+    if (p->h_descs) (void)hipHostFree(p->h_descs);
+    if (p->h_items) (void)hipHostFree(p->h_items);
+    if (p->h_meta) (void)hipHostFree(p->h_meta);
+    delete p;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ldp_batch_plan_create(ldp_batch_plan **out, int32_t max_images, int64_t max_pixels, int32_t k,
+                          int32_t cells_y, int32_t cells_x, const ldp_tune *tune)
+{
+    if (!out || max_images < 1 || max_pixels < 9 || k < 1 || k > 8 || cells_y < 1 ||
+        cells_x < 1 || cells_y > LDP_MAX_SIDE - 2 || cells_x > ldp::kMaxFusedCellsX)
+        return LDP_ERR_INVALID_ARG;
+    *out = nullptr;
+    ldp_batch_plan *p = new (std::nothrow) ldp_batch_plan();
+    if (!p)
+        return LDP_ERR_NO_MEMORY;
+    p->k = k;
+    p->cells_y = cells_y;
+    p->cells_x = cells_x;
+    p->max_images = max_images;
+    p->max_pixels = max_pixels;
+    if (tune) {
+        if (tune->block_threads)
+            p->threads = tune->block_threads;
+        if (tune->cell_rows_per_item)
+            p->cpi = tune->cell_rows_per_item;
+        if (tune->rows_per_task)
+            p->min_task_rows = tune->rows_per_task;
+        if (tune->grid_blocks)
+            p->grid = tune->grid_blocks;
+    }
+    if ((p->threads != 256 && p->threads != 512 && p->threads != 1024) || p->cpi < 1 ||
+        p->min_task_rows < 1 || p->grid < 0) {
+        delete p;
+        return LDP_ERR_INVALID_ARG;
+    }
+    p->cpi = std::min(p->cpi, cells_y);
+    p->max_items = (int64_t)max_images * ((cells_y + p->cpi - 1) / p->cpi);
+    p->lds_bytes = (size_t)p->cpi * cells_x * 256 * sizeof(uint32_t);
+    if (p->lds_bytes > 64 * 1024) {
+        delete p;
+        return LDP_ERR_UNSUPPORTED;
+    }
+    if (hipGetDevice(&p->device) != hipSuccess) {
+        delete p;
+        return LDP_ERR_HIP;
+    }
+    auto fail = [&](int st) {
+        release(p);
+        return st;
+    };
+    if (hipMalloc(&p->d_descs, sizeof(ldp_image_desc) * max_images) != hipSuccess ||
+        hipMalloc(&p->d_items, sizeof(ldp::Item) * p->max_items) != hipSuccess ||
+        hipMalloc(&p->d_meta, 64) != hipSuccess ||
+        hipHostMalloc(&p->h_descs, sizeof(ldp_image_desc) * max_images) != hipSuccess ||
+        hipHostMalloc(&p->h_items, sizeof(ldp::Item) * p->max_items) != hipSuccess ||
+        hipHostMalloc(&p->h_meta, 64) != hipSuccess)
+        return fail(LDP_ERR_NO_MEMORY);
+    if (hipMemset(p->d_meta, 0, 64) != hipSuccess)
+        return fail(LDP_ERR_HIP);
+
+    ldp::batch_fn fn = ldp::batch_kernel_for(k);
+    if (!p->grid) {
+        int per_cu = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(fn),
+                                                         p->threads, p->lds_bytes) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) !=
+                hipSuccess)
+            return fail(LDP_ERR_HIP);
+        p->grid = std::max(1, per_cu) * std::max(1, cus);
+    }
+    if (hipStreamCreate(&p->cap_stream) != hipSuccess ||
+        hipEventCreateWithFlags(&p->uploaded, hipEventDisableTiming) != hipSuccess)
+        return fail(LDP_ERR_HIP);
+    // capture: clear the queue counter, then the persistent kernel
+    if (hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return fail(LDP_ERR_HIP);
+    hipLaunchKernelGGL(ldp::clear_counter_kernel, dim3(1), dim3(1), 0, p->cap_stream, p->d_meta);
+    hipLaunchKernelGGL(fn, dim3(p->grid), dim3(p->threads), p->lds_bytes, p->cap_stream,
+                       (const ldp_image_desc *)p->d_descs, (const ldp::Item *)p->d_items,
+                       p->d_meta, cells_y, cells_x, p->min_task_rows);
+    hipError_t ce = hipStreamEndCapture(p->cap_stream, &p->graph);
+    if (ce != hipSuccess || hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) !=
+                                hipSuccess)
+        return fail(LDP_ERR_HIP);
+    *out = p;
+    return LDP_OK;
+}
+
+int ldp_batch_plan_set(ldp_batch_plan *p, const ldp_image_desc *descs, int32_t n,
+                       ldp_stream_t stream)
+{
+    if (!p || n < 0 || (n > 0 && !descs))
+        return LDP_ERR_INVALID_ARG;
+    if (n > p->max_images)
+        return LDP_ERR_NO_MEMORY;
+    int64_t pixels = 0;
+    for (int32_t j = 0; j < n; ++j) {
+        const ldp_image_desc &d = descs[j];
+        int st = ldp::check_image(d.img, d.H, d.W, d.stride);
+        if (st != LDP_OK)
+            return st;
+        if (!d.hist || d.H - 2 < p->cells_y || d.W - 2 < p->cells_x)
+            return LDP_ERR_INVALID_ARG;
+        pixels += (int64_t)d.H * d.W;
+    }
+    if (pixels > p->max_pixels)
+        return LDP_ERR_NO_MEMORY;
+    // the staging buffers may still feed the previous upload
+    if (hipEventSynchronize(p->uploaded) != hipSuccess)
+        return LDP_ERR_HIP;
+    p->descs.assign(descs, descs + n);
+    // work items: groups of cpi cell rows, largest first
+    std::vector<ldp::Item> items;
+    items.reserve((size_t)n * ((p->cells_y + p->cpi - 1) / p->cpi));
+    std::vector<int64_t> size;
+    for (int32_t j = 0; j < n; ++j) {
+        const int32_t Hc = descs[j].H - 2;
+        for (int32_t cy = 0; cy < p->cells_y; cy += p->cpi) {
+            int32_t cy1 = std::min(cy + p->cpi, p->cells_y);
+            items.push_back({j, (int16_t)cy, (int16_t)cy1});
+            int64_t rows = ldp::cell_start(cy1, Hc, p->cells_y) - ldp::cell_start(cy, Hc, p->cells_y);
+            size.push_back(rows * (descs[j].W - 2));
+        }
+    }
+    std::vector<int64_t> order(items.size());
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int64_t a, int64_t b) { return size[a] > size[b]; });
+    for (size_t i = 0; i < order.size(); ++i)
+        p->h_items[i] = items[order[i]];
+    std::copy(descs, descs + n, p->h_descs);
+    p->n_items = (int64_t)items.size();
+    p->h_meta[0] = (uint32_t)p->n_items;
+    p->h_meta[1] = 0;
+    hipStream_t s = (hipStream_t)stream;
+    if (hipMemcpyAsync(p->d_descs, p->h_descs, sizeof(ldp_image_desc) * n, hipMemcpyHostToDevice,
+                       s) != hipSuccess ||
+        hipMemcpyAsync(p->d_items, p->h_items, sizeof(ldp::Item) * p->n_items,
+                       hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(p->d_meta, p->h_meta, 8, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipEventRecord(p->uploaded, s) != hipSuccess)
+        return LDP_ERR_HIP;
+    return LDP_OK;
+}
+
+int ldp_batch_run(ldp_batch_plan *p, ldp_stream_t stream)
+{
+    if (!p)
+        return LDP_ERR_INVALID_ARG;
+    if (p->n_items == 0)
+        return LDP_OK;
+    return hipGraphLaunch(p->exec, (hipStream_t)stream) == hipSuccess ? LDP_OK : LDP_ERR_HIP;
+}
+
+int ldp_batch_run_per_image(ldp_batch_plan *p, ldp_stream_t stream)
+{
+    if (!p)
+        return LDP_ERR_INVALID_ARG;
+    for (const ldp_image_desc &d : p->descs) {
+        int st = ldp::launch_extract(d.img, d.H, d.W, d.stride, p->k, p->cells_y, p->cells_x,
+                                     d.codes, d.hist, (hipStream_t)stream);
+        if (st != LDP_OK)
+            return st;
+    }
+    return LDP_OK;
+}
+
+int ldp_batch_plan_info(const ldp_batch_plan *p, int64_t *work_items, int32_t *grid_blocks)
+{
+    if (!p)
+        return LDP_ERR_INVALID_ARG;
+    if (work_items)
+        *work_items = p->n_items;
+    if (grid_blocks)
+        *grid_blocks = p->grid;
+    return LDP_OK;
+}
+
+int ldp_batch_plan_destroy(ldp_batch_plan *p)
+{
+    if (!p)
+        return LDP_ERR_INVALID_ARG;
+    (void)hipDeviceSynchronize();
+    release(p);
+    return LDP_OK;
+}
+
+}  // extern "C"

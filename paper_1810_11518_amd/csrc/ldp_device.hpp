@@ -1,0 +1,245 @@
+// ldp_device.hpp -- device building blocks of the gfx950 LDP kernels.
+//
+// One lane is a "column worker": it owns 8 adjacent code columns of one image
+// and walks down a range of code rows with a three-row register window, so
+// every image byte it needs is loaded once per row (plus a one-byte halo on
+// each side, loaded in the same dwords).
+//
+// Arithmetic (exact integers throughout):
+//   * Section 2.3 removes the redundancy of the eight 3x3 mask products by
+//     sharing column partial sums between masks (Eqs. 7-29).  Taken to its
+//     end, every Kirsch response is m_i = 8*S_i - 3*T, where S_i is the sum of
+//     the three ring neighbours that mask i weighs with +5 (ring order E, NE,
+//     N, NW, W, SW, S, SE; S_i = p_{i-1} + p_i + p_{i+1}) and T is the sum of
+//     all eight neighbours.  T is common to the eight responses of a pixel, so
+//     the order of the responses, the k-th largest one and every tie are
+//     those of the S_i.  The code of Eqs. 2-3 is therefore computed from the
+//     S_i alone: bit i is set when S_i >= (k-th largest S).
+//   * The S_i of neighbouring pixels share partial sums: S0 and S4 are column
+//     3-sums (the right and left columns), S2 and S6 are row 3-sums (the rows
+//     above and below), and the four corner triples are a vertical pair sum
+//     plus one pixel.  Each column 3-sum serves two pixels, each row 3-sum two
+//     rows, each vertical pair four corner triples.
+//   * S_i <= 765 fits 16 bits, so two pixels share one 32-bit register.  No
+//     sum can carry out of its 16-bit field, so sums are plain 32-bit adds
+//     (on gfx950 v_add_u32 issues at twice the rate of v_pk_add_u16); only
+//     min/max use packed 16-bit instructions (v_pk_max_u16, v_pk_min_u16).
+//     The 8 pixels of a lane are held as four pairs (c, c+4), c = 0..3,
+//     which makes the left and right neighbours of each pair another pair.
+//   * The k-th largest of eight values is a branch-free min/max network
+//     (for k = 3, the sorted top three of each half, merged).
+//   * The code bits are the sign bits of S_i + 0x8000 - t (bit 15 of a field
+//     is set exactly when S_i >= t, and no field can carry): v_perm_b32
+//     gathers four of them into four byte masks at once and v_bitop3_b32
+//     merges the eight directions.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ldp {
+
+typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ u16x2 V(uint32_t x) { return __builtin_bit_cast(u16x2, x); }
+__device__ __forceinline__ uint32_t U(u16x2 v) { return __builtin_bit_cast(uint32_t, v); }
+__device__ __forceinline__ u16x2 vmax(u16x2 a, u16x2 b) { return __builtin_elementwise_max(a, b); }
+__device__ __forceinline__ u16x2 vmin(u16x2 a, u16x2 b) { return __builtin_elementwise_min(a, b); }
+
+// ------------------------------------------------------------ k-th largest
+// Eq. 2's m_k: the k-th element of the eight values in descending order,
+// duplicates kept.  Split into halves A = s0..s3 and B = s4..s7; the k-th
+// largest of A u B is max over i + j = k of min(A_(i), B_(j)), with
+// A_(0) = B_(0) = +infinity and A_(i) the i-th largest of A.
+
+struct Sorted4 {
+    u16x2 v[5];  // v[1] >= v[2] >= v[3] >= v[4]; v[0] = +inf
+};
+
+__device__ __forceinline__ Sorted4 sort4(u16x2 a, u16x2 b, u16x2 c, u16x2 d)
+{
+    u16x2 h0 = vmax(a, b), l0 = vmin(a, b);
+    u16x2 h1 = vmax(c, d), l1 = vmin(c, d);
+    Sorted4 s;
+    s.v[0] = V(0xFFFFFFFFu);
+    s.v[1] = vmax(h0, h1);
+    u16x2 mh = vmin(h0, h1), ml = vmax(l0, l1);
+    s.v[2] = vmax(mh, ml);
+    s.v[3] = vmin(mh, ml);
+    s.v[4] = vmin(l0, l1);
+    return s;
+}
+
+template <int K>
+__device__ __forceinline__ u16x2 kth_largest(const u16x2 (&s)[8])
+{
+    static_assert(K >= 1 && K <= 8, "k in 1..8");
+    if constexpr (K == 3) {
+        // sorted top three of each half, then
+        // m_3 = max(A_(3), B_(3), min(A_(1), B_(2)), min(A_(2), B_(1)))
+        u16x2 h0 = vmax(s[0], s[1]), l0 = vmin(s[0], s[1]);
+        u16x2 h1 = vmax(s[2], s[3]), l1 = vmin(s[2], s[3]);
+        u16x2 x1 = vmax(h0, h1), mh = vmin(h0, h1), ml = vmax(l0, l1);
+        u16x2 x2 = vmax(mh, ml), x3 = vmin(mh, ml);
+        u16x2 g0 = vmax(s[4], s[5]), k0 = vmin(s[4], s[5]);
+        u16x2 g1 = vmax(s[6], s[7]), k1 = vmin(s[6], s[7]);
+        u16x2 y1 = vmax(g0, g1), nh = vmin(g0, g1), nl = vmax(k0, k1);
+        u16x2 y2 = vmax(nh, nl), y3 = vmin(nh, nl);
+        return vmax(vmax(x3, y3), vmax(vmin(x1, y2), vmin(x2, y1)));
+    } else if constexpr (K == 2) {
+        // m_2 = max(A_(2), B_(2), min(A_(1), B_(1)))
+        u16x2 h0 = vmax(s[0], s[1]), l0 = vmin(s[0], s[1]);
+        u16x2 h1 = vmax(s[2], s[3]), l1 = vmin(s[2], s[3]);
+        u16x2 x1 = vmax(h0, h1), x2 = vmax(vmin(h0, h1), vmax(l0, l1));
+        u16x2 g0 = vmax(s[4], s[5]), k0 = vmin(s[4], s[5]);
+        u16x2 g1 = vmax(s[6], s[7]), k1 = vmin(s[6], s[7]);
+        u16x2 y1 = vmax(g0, g1), y2 = vmax(vmin(g0, g1), vmax(k0, k1));
+        return vmax(vmax(x2, y2), vmin(x1, y1));
+    } else if constexpr (K == 1) {
+        return vmax(vmax(vmax(s[0], s[1]), vmax(s[2], s[3])),
+                    vmax(vmax(s[4], s[5]), vmax(s[6], s[7])));
+    } else {
+        Sorted4 A = sort4(s[0], s[1], s[2], s[3]);
+        Sorted4 B = sort4(s[4], s[5], s[6], s[7]);
+        constexpr int lo = K > 4 ? K - 4 : 0;
+        constexpr int hi = K < 4 ? K : 4;
+        u16x2 t = vmin(A.v[lo], B.v[K - lo]);
+#pragma unroll
+        for (int i = lo + 1; i <= hi; ++i)
+            t = vmax(t, vmin(A.v[i], B.v[K - i]));
+        return t;
+    }
+}
+
+// ------------------------------------------------------------ image rows
+// One image row as seen by a lane: bytes B[0..9] = image columns j0..j0+9,
+// held as six pairs X[a] = (B[a], B[a+4]).  Pixel pair c (c = 0..3) is
+// centred on X[c+1]; its left and right neighbour columns are X[c] and
+// X[c+2].  R[c] is the row 3-sum of pair c.
+struct Row {
+    uint32_t X[6];
+    uint32_t R[4];
+};
+
+__device__ __forceinline__ uint32_t pair_sel(int a)
+{
+    // bytes: [lo.a, 0, hi.a, 0] from {src0 = hi word, src1 = lo word}
+    return (uint32_t)a | (0x0Cu << 8) | ((uint32_t)(4 + a) << 16) | (0x0Cu << 24);
+}
+
+__device__ __forceinline__ void make_row(Row &r, uint32_t u0, uint32_t u1, uint32_t u2)
+{
+    r.X[0] = __builtin_amdgcn_perm(u1, u0, pair_sel(0));
+    r.X[1] = __builtin_amdgcn_perm(u1, u0, pair_sel(1));
+    r.X[2] = __builtin_amdgcn_perm(u1, u0, pair_sel(2));
+    r.X[3] = __builtin_amdgcn_perm(u1, u0, pair_sel(3));
+    r.X[4] = __builtin_amdgcn_perm(u2, u1, pair_sel(0));
+    r.X[5] = __builtin_amdgcn_perm(u2, u1, pair_sel(1));
+    // two 16-bit fields per add; no field exceeds 765, so nothing carries
+    uint32_t h1 = r.X[1] + r.X[2];
+    uint32_t h3 = r.X[3] + r.X[4];
+    r.R[0] = r.X[0] + h1;
+    r.R[1] = h1 + r.X[3];
+    r.R[2] = r.X[2] + h3;
+    r.R[3] = h3 + r.X[5];
+}
+
+// Raw words of one row: 16 bytes starting at the 4-aligned offset at or
+// below the lane's first byte, plus the shift s (0..3) to the first byte.
+struct RawRow {
+    uint32_t w[4];
+    uint32_t s;
+};
+
+template <bool ALIGNED>
+__device__ __forceinline__ void load_row(RawRow &rr, __amdgpu_buffer_rsrc_t rsrc, uint32_t off)
+{
+    if constexpr (ALIGNED) {
+        rr.s = 0;
+        rr.w[0] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)off, 0, 0);
+        rr.w[1] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)(off + 4), 0, 0);
+        rr.w[2] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)(off + 8), 0, 0);
+        rr.w[3] = 0;
+    } else {
+        rr.s = off & 3u;
+        uint32_t a = off & ~3u;
+        rr.w[0] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)a, 0, 0);
+        rr.w[1] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)(a + 4), 0, 0);
+        rr.w[2] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)(a + 8), 0, 0);
+        rr.w[3] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)(a + 12), 0, 0);
+    }
+}
+
+template <bool ALIGNED>
+__device__ __forceinline__ void unpack_row(Row &r, const RawRow &rr)
+{
+    if constexpr (ALIGNED) {
+        make_row(r, rr.w[0], rr.w[1], rr.w[2]);
+    } else {
+        uint32_t u0 = __builtin_amdgcn_alignbyte(rr.w[1], rr.w[0], rr.s);
+        uint32_t u1 = __builtin_amdgcn_alignbyte(rr.w[2], rr.w[1], rr.s);
+        uint32_t u2 = __builtin_amdgcn_alignbyte(rr.w[3], rr.w[2], rr.s);
+        make_row(r, u0, u1, u2);
+    }
+}
+
+// ------------------------------------------------------------ one code row
+// Codes of the lane's 8 pixels for the code row whose image rows are t
+// (above), m (centre) and b (below).  Vt[a] = X_t[a] + X_m[a] and
+// Vb[a] = X_m[a] + X_b[a] are the vertical pair sums.  Returns the codes of
+// pixels 0..3 in `lo` and 4..7 in `hi` (byte p = pixel p).
+template <int K>
+__device__ __forceinline__ void code_row(const Row &t, const Row &b, const uint32_t (&Vt)[6],
+                                         const uint32_t (&Vb)[6], uint32_t &lo, uint32_t &hi)
+{
+    if constexpr (K == 8) {
+        // the 8th largest is the minimum: every response reaches it
+        lo = hi = 0xFFFFFFFFu;
+        return;
+    } else {
+        uint32_t col[6];
+#pragma unroll
+        for (int a = 0; a < 6; ++a)
+            col[a] = Vt[a] + b.X[a];
+
+        uint32_t d[4][8];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int a = c + 1;
+            uint32_t S[8];
+            S[0] = col[a + 1];           // E   column to the right
+            S[1] = Vt[a + 1] + t.X[a];   // NE  E + NE + N
+            S[2] = t.R[c];               // N   row above
+            S[3] = Vt[a - 1] + t.X[a];   // NW  N + NW + W
+            S[4] = col[a - 1];           // W   column to the left
+            S[5] = Vb[a - 1] + b.X[a];   // SW  W + SW + S
+            S[6] = b.R[c];               // S   row below
+            S[7] = Vb[a + 1] + b.X[a];   // SE  S + SE + E
+            u16x2 Sv[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                Sv[i] = V(S[i]);
+            const uint32_t thr = U(kth_largest<K>(Sv));
+            const uint32_t bias = 0x80008000u - thr;  // 0x8000 - thr per field
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                d[c][i] = S[i] + bias;  // bit 15 of a field set iff S_i >= thr
+        }
+        // Byte masks: M01 = [px0, px1, px4, px5], M23 = [px2, px3, px6, px7],
+        // 0xFF where S_i >= thr (the sign selectors 8..11 of v_perm_b32),
+        // merged bit by bit: bit i of every byte from direction i.
+        uint32_t c01 = __builtin_amdgcn_perm(d[1][0], d[0][0], 0x0B090A08u);
+        uint32_t c23 = __builtin_amdgcn_perm(d[3][0], d[2][0], 0x0B090A08u);
+#pragma unroll
+        for (int i = 1; i < 8; ++i) {
+            const uint32_t m = 0x01010101u << i;
+            uint32_t m01 = __builtin_amdgcn_perm(d[1][i], d[0][i], 0x0B090A08u);
+            uint32_t m23 = __builtin_amdgcn_perm(d[3][i], d[2][i], 0x0B090A08u);
+            c01 = __builtin_amdgcn_bitop3_b32(m, m01, c01, 0xCA);  // m ? m01 : c01
+            c23 = __builtin_amdgcn_bitop3_b32(m, m23, c23, 0xCA);
+        }
+        lo = __builtin_amdgcn_perm(c23, c01, 0x05040100u);
+        hi = __builtin_amdgcn_perm(c23, c01, 0x07060302u);
+    }
+}
+
+}  // namespace ldp

@@ -1,0 +1,44 @@
+// ldp_host.hpp -- host-side argument checks and launch helpers shared by the
+// single-image entry points, the batch plan and the server.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+#include "../../include/ldp.h"
+
+namespace ldp {
+
+// Largest byte extent of one image that the 32-bit buffer offsets address.
+constexpr int64_t kMaxExtent = (int64_t(1) << 31) - 64;
+
+inline int check_image(const uint8_t *img, int32_t H, int32_t W, int64_t stride)
+{
+    if (!img || H < 3 || W < 3 || H > LDP_MAX_SIDE || W > LDP_MAX_SIDE || stride < W)
+        return LDP_ERR_INVALID_ARG;
+    if ((int64_t)(H - 1) * stride + W + 8 > kMaxExtent)
+        return LDP_ERR_UNSUPPORTED;
+    return LDP_OK;
+}
+
+inline int check_cells(int32_t H, int32_t W, int32_t cells_y, int32_t cells_x)
+{
+    if (cells_y < 1 || cells_x < 1 || cells_y > H - 2 || cells_x > W - 2)
+        return LDP_ERR_INVALID_ARG;
+    return LDP_OK;
+}
+
+// Largest cells_x the fused kernels keep in LDS (one cell row, 1 KiB per cell).
+constexpr int32_t kMaxFusedCellsX = 64;
+
+bool image_aligned(const uint8_t *img, int64_t stride);
+int launch_codes(const uint8_t *img, int32_t H, int32_t W, int64_t stride, int32_t k,
+                 uint8_t *codes, hipStream_t s);
+int launch_histograms(const uint8_t *codes, int32_t H, int32_t W, int32_t cells_y,
+                      int32_t cells_x, uint32_t *hist, hipStream_t s);
+int launch_extract(const uint8_t *img, int32_t H, int32_t W, int64_t stride, int32_t k,
+                   int32_t cells_y, int32_t cells_x, uint8_t *codes, uint32_t *hist,
+                   hipStream_t s);
+
+}  // namespace ldp

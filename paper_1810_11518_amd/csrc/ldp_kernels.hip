@@ -1,0 +1,255 @@
+// ldp_kernels.hip -- single-image LDP kernels and their C ABI entry points.
+//
+//   ldp_codes       codes of every interior pixel (Eqs. 1-3)
+//   ldp_histograms  per-cell 256-bin histograms of a code map (Eqs. 4-5)
+//   ldp_extract     both in one launch, without reading the codes back
+#include "ldp_engine.hpp"
+#include "ldp_host.hpp"
+
+#ifndef LDP_CODES_LANES
+#define LDP_CODES_LANES 524288
+#endif
+#ifndef LDP_CODES_MIN_BAND
+#define LDP_CODES_MIN_BAND 8
+#endif
+
+namespace ldp {
+
+// ---------------------------------------------------------------- codes
+// One thread per task: task = (row band, column group).
+template <int K, bool ALIGNED>
+__global__ void __launch_bounds__(256) codes_kernel(const uint8_t *__restrict__ img,
+                                                    int64_t stride, int32_t H, int32_t W,
+                                                    uint8_t *__restrict__ codes, int32_t band_rows,
+                                                    int32_t ngroups, int32_t ntasks)
+{
+    int32_t task = blockIdx.x * blockDim.x + threadIdx.x;
+    if (task >= ntasks)
+        return;
+    ImgView im = make_view(img, stride, H, W, codes);
+    int32_t g = task % ngroups;
+    int32_t band = task / ngroups;
+    int32_t r0 = band * band_rows;
+    int32_t r1 = min(r0 + band_rows, im.Hc);
+    HistWin hw{};
+    run_task<K, ALIGNED, false>(im, hw, g, r0, r1);
+}
+
+// ---------------------------------------------------------------- histograms
+// Block (cx, cy, split) counts the codes of cell (cy, cx), rows split in
+// `nsplit` parts.  Wave-private LDS bins; one store (or atomic add when the
+// cell is split) per bin.
+__global__ void __launch_bounds__(256) hist_kernel(const uint8_t *__restrict__ codes, int32_t Hc,
+                                                   int32_t Wc, int32_t cells_y, int32_t cells_x,
+                                                   uint32_t *__restrict__ hist, int32_t nsplit)
+{
+    __shared__ uint32_t bins[4][256];
+    const int tid = threadIdx.x, wave = tid >> 6;
+#pragma unroll
+    for (int w = 0; w < 4; ++w)
+        bins[w][tid] = 0;
+    __syncthreads();
+    const int32_t cx = blockIdx.x, cy = blockIdx.y, sp = blockIdx.z;
+    const int32_t ry0 = cell_start(cy, Hc, cells_y), ry1 = cell_start(cy + 1, Hc, cells_y);
+    const int32_t c0 = cell_start(cx, Wc, cells_x), c1 = cell_start(cx + 1, Wc, cells_x);
+    const int32_t nrows = ry1 - ry0, width = c1 - c0;
+    const int32_t a0 = ry0 + (int32_t)((int64_t)nrows * sp / nsplit);
+    const int32_t a1 = ry0 + (int32_t)((int64_t)nrows * (sp + 1) / nsplit);
+    const int64_t n = (int64_t)(a1 - a0) * width;
+    for (int64_t idx = tid; idx < n; idx += 256) {
+        int32_t r = a0 + (int32_t)(idx / width);
+        int32_t c = c0 + (int32_t)(idx % width);
+        atomicAdd(&bins[wave][codes[(int64_t)r * Wc + c]], 1u);
+    }
+    __syncthreads();
+    uint32_t total = bins[0][tid] + bins[1][tid] + bins[2][tid] + bins[3][tid];
+    uint32_t *dst = hist + ((int64_t)cy * cells_x + cx) * 256 + tid;
+    if (nsplit == 1)
+        *dst = total;
+    else if (total)
+        atomicAdd(dst, total);
+}
+
+__global__ void zero_kernel(uint32_t *__restrict__ p, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+// ---------------------------------------------------------------- fused
+template <int K, bool ALIGNED>
+__global__ void __launch_bounds__(1024) fused_kernel(const uint8_t *__restrict__ img,
+                                                     int64_t stride, int32_t H, int32_t W,
+                                                     uint8_t *codes, uint32_t *hist,
+                                                     int32_t cells_y, int32_t cells_x,
+                                                     int32_t split)
+{
+    extern __shared__ uint32_t lds[];
+    ImgView im = make_view(img, stride, H, W, codes);
+    const int32_t cy = blockIdx.x / split, sp = blockIdx.x % split;
+    const int32_t ry0 = cell_start(cy, im.Hc, cells_y), ry1 = cell_start(cy + 1, im.Hc, cells_y);
+    const int32_t r0 = ry0 + (int32_t)((int64_t)(ry1 - ry0) * sp / split);
+    const int32_t r1 = ry0 + (int32_t)((int64_t)(ry1 - ry0) * (sp + 1) / split);
+    fused_item<K, ALIGNED>(im, lds, cells_y, cells_x, cy, cy + 1, r0, r1, hist, split > 1, 4);
+}
+
+// ---------------------------------------------------------------- dispatch
+template <template <int, bool> class F, typename... Args>
+static hipError_t dispatch_k(int k, bool aligned, Args &&...args)
+{
+    switch (k) {
+#define LDP_CASE(KK)                                                           \
+    case KK:                                                                   \
+        return aligned ? F<KK, true>::launch(args...) : F<KK, false>::launch(args...);
+        LDP_CASE(1) LDP_CASE(2) LDP_CASE(3) LDP_CASE(4)
+        LDP_CASE(5) LDP_CASE(6) LDP_CASE(7) LDP_CASE(8)
+#undef LDP_CASE
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int K, bool AL>
+struct CodesLaunch {
+    static hipError_t launch(dim3 grid, dim3 block, hipStream_t s, const uint8_t *img,
+                             int64_t stride, int32_t H, int32_t W, uint8_t *codes, int32_t band,
+                             int32_t ngroups, int32_t ntasks)
+    {
+        hipLaunchKernelGGL((codes_kernel<K, AL>), grid, block, 0, s, img, stride, H, W, codes,
+                           band, ngroups, ntasks);
+        return hipGetLastError();
+    }
+};
+
+template <int K, bool AL>
+struct FusedLaunch {
+    static hipError_t launch(dim3 grid, dim3 block, size_t lds, hipStream_t s, const uint8_t *img,
+                             int64_t stride, int32_t H, int32_t W, uint8_t *codes,
+                             uint32_t *hist, int32_t cells_y, int32_t cells_x, int32_t split)
+    {
+        hipLaunchKernelGGL((fused_kernel<K, AL>), grid, block, lds, s, img, stride, H, W, codes,
+                           hist, cells_y, cells_x, split);
+        return hipGetLastError();
+    }
+};
+
+bool image_aligned(const uint8_t *img, int64_t stride)
+{
+    return ((uintptr_t)img & 3u) == 0 && (stride & 3) == 0;
+}
+
+int launch_codes(const uint8_t *img, int32_t H, int32_t W, int64_t stride, int32_t k,
+                 uint8_t *codes, hipStream_t s)
+{
+    const int32_t Hc = H - 2, Wc = W - 2;
+    const int32_t ngroups = (Wc + 7) / 8;
+    // band height: enough lanes to keep every SIMD several waves deep
+    int64_t lanes_rows = (int64_t)ngroups * Hc;
+    int32_t band = (int32_t)std::min<int64_t>(64, std::max<int64_t>(LDP_CODES_MIN_BAND, lanes_rows / LDP_CODES_LANES + 1));
+    int32_t nbands = (Hc + band - 1) / band;
+    int32_t ntasks = ngroups * nbands;
+    dim3 block(256), grid((ntasks + 255) / 256);
+    hipError_t e = dispatch_k<CodesLaunch>(k, image_aligned(img, stride), grid, block, s, img,
+                                           stride, H, W, codes, band, ngroups, ntasks);
+    return e == hipSuccess ? LDP_OK : LDP_ERR_HIP;
+}
+
+int launch_histograms(const uint8_t *codes, int32_t H, int32_t W, int32_t cells_y,
+                      int32_t cells_x, uint32_t *hist, hipStream_t s)
+{
+    const int32_t Hc = H - 2, Wc = W - 2;
+    const int64_t cells = (int64_t)cells_y * cells_x;
+    const int64_t per_cell = (int64_t)Hc * Wc / cells;
+    // split cells so that there are enough workgroups and none is huge
+    int32_t nsplit = 1;
+    while (nsplit < 64 && (cells * nsplit < 512 || per_cell / nsplit > (1 << 16)) &&
+           (Hc / cells_y) / (nsplit * 2) >= 1)
+        nsplit *= 2;
+    if (nsplit > 1) {
+        int64_t n = cells * 256;
+        hipLaunchKernelGGL(zero_kernel, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 1024)),
+                           dim3(256), 0, s, hist, n);
+    }
+    hipLaunchKernelGGL(hist_kernel, dim3(cells_x, cells_y, nsplit), dim3(256), 0, s, codes, Hc,
+                       Wc, cells_y, cells_x, hist, nsplit);
+    return hipGetLastError() == hipSuccess ? LDP_OK : LDP_ERR_HIP;
+}
+
+// LDS bytes of one cell row of histograms
+static size_t fused_lds_bytes(int32_t cells_x) { return (size_t)cells_x * 256 * 4; }
+
+int launch_extract(const uint8_t *img, int32_t H, int32_t W, int64_t stride, int32_t k,
+                   int32_t cells_y, int32_t cells_x, uint8_t *codes, uint32_t *hist,
+                   hipStream_t s)
+{
+    const int32_t Hc = H - 2, Wc = W - 2;
+    if (cells_x > kMaxFusedCellsX) {
+        // one cell row of histograms does not fit in LDS: two passes
+        if (!codes)
+            return LDP_ERR_UNSUPPORTED;
+        int st = launch_codes(img, H, W, stride, k, codes, s);
+        return st != LDP_OK ? st : launch_histograms(codes, H, W, cells_y, cells_x, hist, s);
+    }
+    const int32_t ngroups = (Wc + 7) / 8;
+    int threads = ngroups >= 768 ? 1024 : ngroups >= 384 ? 512 : 256;
+    // enough workgroups to fill the device: split cell rows
+    int32_t split = 1;
+    const int32_t rows_per_cell = Hc / cells_y;
+    while ((int64_t)cells_y * split < 512 && rows_per_cell / (split * 2) >= 8 && split < 64)
+        split *= 2;
+    if (split > 1) {
+        int64_t n = (int64_t)cells_y * cells_x * 256;
+        hipLaunchKernelGGL(zero_kernel, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 1024)),
+                           dim3(256), 0, s, hist, n);
+    }
+    size_t lds = fused_lds_bytes(cells_x);
+    hipError_t e = dispatch_k<FusedLaunch>(k, image_aligned(img, stride),
+                                           dim3(cells_y * split), dim3(threads), lds, s, img,
+                                           stride, H, W, codes, hist, cells_y, cells_x, split);
+    return e == hipSuccess ? LDP_OK : LDP_ERR_HIP;
+}
+
+}  // namespace ldp
+
+// ---------------------------------------------------------------- C ABI
+extern "C" {
+
+int ldp_codes(const uint8_t *img, int32_t H, int32_t W, int64_t stride, int32_t k,
+              uint8_t *codes, ldp_stream_t stream)
+{
+    int st = ldp::check_image(img, H, W, stride);
+    if (st != LDP_OK)
+        return st;
+    if (!codes || k < 1 || k > 8)
+        return LDP_ERR_INVALID_ARG;
+    return ldp::launch_codes(img, H, W, stride, k, codes, (hipStream_t)stream);
+}
+
+int ldp_histograms(const uint8_t *codes, int32_t H, int32_t W, int32_t cells_y,
+                   int32_t cells_x, uint32_t *hist, ldp_stream_t stream)
+{
+    if (!codes || !hist || H < 3 || W < 3 || H > LDP_MAX_SIDE || W > LDP_MAX_SIDE)
+        return LDP_ERR_INVALID_ARG;
+    int st = ldp::check_cells(H, W, cells_y, cells_x);
+    if (st != LDP_OK)
+        return st;
+    return ldp::launch_histograms(codes, H, W, cells_y, cells_x, hist, (hipStream_t)stream);
+}
+
+int ldp_extract(const uint8_t *img, int32_t H, int32_t W, int64_t stride, int32_t k,
+                int32_t cells_y, int32_t cells_x, uint8_t *codes, uint32_t *hist,
+                ldp_stream_t stream)
+{
+    int st = ldp::check_image(img, H, W, stride);
+    if (st != LDP_OK)
+        return st;
+    if (!hist || k < 1 || k > 8)
+        return LDP_ERR_INVALID_ARG;
+    st = ldp::check_cells(H, W, cells_y, cells_x);
+    if (st != LDP_OK)
+        return st;
+    return ldp::launch_extract(img, H, W, stride, k, cells_y, cells_x, codes, hist,
+                               (hipStream_t)stream);
+}
+
+}  // extern "C"

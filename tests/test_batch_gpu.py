@@ -1,0 +1,151 @@
+"""The persistent, graph-captured batch launch against the oracle."""
+import numpy as np
+import pytest
+
+from conftest import gpu_available
+from oracle import native as oracle_c
+from paper_1810_11518_amd import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not gpu_available():
+        pytest.skip("no GPU")
+    from paper_1810_11518_amd import binding
+    binding.load()
+    return binding
+
+
+class Batch:
+    """Images packed back to back in one device buffer, with outputs."""
+
+    def __init__(self, Hs, Ws, kind, seed, cells, row_align=1, shift=0, with_codes=True):
+        self.Hs, self.Ws = np.asarray(Hs), np.asarray(Ws)
+        off, strides, total = synth.layout(self.Hs, self.Ws, row_align=row_align)
+        off = off + shift
+        host = np.zeros(total + shift + 64, np.uint8)
+        synth.fill(host, off, self.Hs, self.Ws, strides, kind, seed)
+        self.host, self.off, self.strides = host, off, strides
+        self.dev = torch.from_numpy(host).cuda()
+        n = len(Hs)
+        self.codes = [torch.full(((h - 2) * (w - 2),), 0xAB, dtype=torch.uint8, device="cuda")
+                      if with_codes else None for h, w in zip(Hs, Ws)]
+        cy, cx = cells
+        self.hist = [torch.full((cy * cx * 256,), 7, dtype=torch.int32, device="cuda")
+                     for _ in range(n)]
+        base = self.dev.data_ptr()
+        self.descs_args = ([base + int(o) for o in off],
+                           [c.data_ptr() if c is not None else None for c in self.codes],
+                           [h.data_ptr() for h in self.hist], [int(s) for s in strides],
+                           [int(h) for h in Hs], [int(w) for w in Ws])
+
+    def image(self, j):
+        H, W, s, o = int(self.Hs[j]), int(self.Ws[j]), int(self.strides[j]), int(self.off[j])
+        return self.host[o:o + H * s].reshape(H, s)[:, :W]
+
+    def check(self, j, k, cells, codes=True):
+        img = self.image(j)
+        want_c, want_h = oracle_c.ldp_extract(img, k, *cells)
+        if codes:
+            got_c = self.codes[j].cpu().numpy().reshape(want_c.shape)
+            assert (got_c == want_c).all(), ("codes", j, img.shape)
+        got_h = self.hist[j].cpu().numpy().view(np.uint32).reshape(want_h.shape)
+        assert (got_h == want_h).all(), ("hist", j, img.shape)
+
+
+def _plan(lib, b, k, cells, tune=None):
+    n = len(b.Hs)
+    pixels = int((b.Hs.astype(np.int64) * b.Ws).sum())
+    plan = lib.BatchPlan(max(n, 1), max(pixels, 9), k, cells[0], cells[1], tune)
+    plan.set(lib.BatchPlan.descs(*b.descs_args))
+    return plan
+
+
+@pytest.mark.parametrize("k", [2, 3, 4])
+def test_uneven_batch_matches_oracle(lib, k):
+    r = np.random.default_rng(k)
+    n = 60
+    Hs = r.integers(9, 400, n)
+    Ws = r.integers(9, 700, n)
+    Hs[:3], Ws[:3] = [490, 9, 1024], [640, 1024, 9]
+    b = Batch(Hs, Ws, synth.KIND_BLUR_RECTS, 31 + k, (7, 6))
+    plan = _plan(lib, b, k, (7, 6))
+    plan.run()
+    torch.cuda.synchronize()
+    for j in range(n):
+        b.check(j, k, (7, 6))
+
+
+@pytest.mark.parametrize("tune", [dict(block_threads=256), dict(block_threads=1024, rows_per_task=16),
+                                  dict(cell_rows_per_item=3, block_threads=512),
+                                  dict(cell_rows_per_item=7, grid_blocks=5)])
+def test_tunings_give_identical_results(lib, tune):
+    r = np.random.default_rng(7)
+    n = 24
+    Hs, Ws = r.integers(20, 300, n), r.integers(20, 300, n)
+    b = Batch(Hs, Ws, synth.KIND_BLUR_SP_FLAT, 5, (7, 6), row_align=4)
+    plan = _plan(lib, b, 3, (7, 6), tune)
+    plan.run()
+    torch.cuda.synchronize()
+    for j in range(n):
+        b.check(j, 3, (7, 6))
+
+
+def test_graph_replay_with_new_batch_and_determinism(lib):
+    r = np.random.default_rng(11)
+    b1 = Batch(r.integers(30, 200, 20), r.integers(30, 200, 20), synth.KIND_BLUR_RECTS, 1, (4, 4))
+    b2 = Batch(r.integers(30, 200, 35), r.integers(30, 200, 35), synth.KIND_BLUR_RECTS, 2, (4, 4),
+               shift=1)
+    plan = lib.BatchPlan(64, 10 ** 7, 3, 4, 4)
+    plan.set(lib.BatchPlan.descs(*b1.descs_args))
+    plan.run()
+    torch.cuda.synchronize()
+    first = [h.clone() for h in b1.hist]
+    for j in range(20):
+        b1.check(j, 3, (4, 4))
+    plan.set(lib.BatchPlan.descs(*b2.descs_args))
+    plan.run()
+    torch.cuda.synchronize()
+    for j in range(35):
+        b2.check(j, 3, (4, 4))
+    plan.set(lib.BatchPlan.descs(*b1.descs_args))
+    for _ in range(3):
+        plan.run()
+    torch.cuda.synchronize()
+    for j in range(20):
+        assert torch.equal(first[j], b1.hist[j])
+
+
+def test_histograms_only_batch(lib):
+    r = np.random.default_rng(12)
+    b = Batch(r.integers(10, 150, 16), r.integers(10, 150, 16), synth.KIND_BLUR_RECTS, 3, (7, 6),
+              with_codes=False)
+    plan = _plan(lib, b, 3, (7, 6))
+    plan.run()
+    torch.cuda.synchronize()
+    for j in range(16):
+        b.check(j, 3, (7, 6), codes=False)
+
+
+def test_per_image_path_matches_batched(lib):
+    r = np.random.default_rng(13)
+    Hs, Ws = r.integers(10, 500, 12), r.integers(10, 500, 12)
+    b = Batch(Hs, Ws, synth.KIND_BLUR_RECTS, 4, (7, 6))
+    plan = _plan(lib, b, 3, (7, 6))
+    plan.run_per_image()
+    torch.cuda.synchronize()
+    for j in range(12):
+        b.check(j, 3, (7, 6))
+
+
+def test_plan_rejects_bad_batches(lib):
+    b = Batch([50, 2 + 5], [50, 60], synth.KIND_UNIFORM, 1, (7, 6))
+    plan = lib.BatchPlan(4, 10 ** 6, 3, 7, 6)
+    with pytest.raises(lib.LdpError):           # second image has fewer code rows than cells
+        plan.set(lib.BatchPlan.descs(*b.descs_args))
+    big = Batch([100] * 5, [100] * 5, synth.KIND_UNIFORM, 1, (7, 6))
+    with pytest.raises(lib.LdpError):           # more images than the plan holds
+        plan.set(lib.BatchPlan.descs(*big.descs_args))
