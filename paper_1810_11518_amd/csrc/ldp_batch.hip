@@ -25,8 +25,12 @@ struct Item {
 
 __global__ void clear_counter_kernel(uint32_t *meta) { meta[1] = 0; }
 
+#ifndef LDP_BATCH_ATTR
+#define LDP_BATCH_ATTR
+#endif
+
 template <int K>
-__global__ void __launch_bounds__(1024) batch_kernel(const ldp_image_desc *__restrict__ descs,
+__global__ void __launch_bounds__(1024) LDP_BATCH_ATTR batch_kernel(const ldp_image_desc *__restrict__ descs,
                                                      const Item *__restrict__ items,
                                                      uint32_t *meta, int32_t cells_y,
                                                      int32_t cells_x, int32_t min_task_rows)
@@ -47,12 +51,9 @@ __global__ void __launch_bounds__(1024) batch_kernel(const ldp_image_desc *__res
         ImgView im = make_view(d.img, d.stride, d.H, d.W, d.codes);
         const int32_t r0 = cell_start(w.cy0, im.Hc, cells_y);
         const int32_t r1 = cell_start(w.cy1, im.Hc, cells_y);
-        if (image_aligned_dev(d.img, d.stride))
-            fused_item<K, true>(im, lds, cells_y, cells_x, w.cy0, w.cy1, r0, r1, d.hist, false,
-                                min_task_rows);
-        else
-            fused_item<K, false>(im, lds, cells_y, cells_x, w.cy0, w.cy1, r0, r1, d.hist, false,
-                                 min_task_rows);
+        // a null code pointer gives an empty store range: stores are dropped
+        fused_item<K, true>(im, lds, cells_y, cells_x, w.cy0, w.cy1, r0, r1, d.hist, false,
+                            min_task_rows);
     }
 }
 
@@ -79,7 +80,7 @@ static batch_fn batch_kernel_for(int k)
 struct ldp_batch_plan {
     int32_t k = 3, cells_y = 1, cells_x = 1, max_images = 0;
     int64_t max_pixels = 0, max_items = 0;
-    int32_t threads = 512, cpi = 1, min_task_rows = 4, grid = 0;
+    int32_t threads = 256, cpi = 1, min_task_rows = 8, grid = 0;
     size_t lds_bytes = 0;
     int device = 0;
     ldp_image_desc *d_descs = nullptr;
@@ -151,7 +152,7 @@ int ldp_batch_plan_create(ldp_batch_plan **out, int32_t max_images, int64_t max_
     }
     p->cpi = std::min(p->cpi, cells_y);
     p->max_items = (int64_t)max_images * ((cells_y + p->cpi - 1) / p->cpi);
-    p->lds_bytes = (size_t)p->cpi * cells_x * 256 * sizeof(uint32_t);
+    p->lds_bytes = (size_t)(p->cpi * cells_x + 1) * 256 * sizeof(uint32_t);
     if (p->lds_bytes > 64 * 1024) {
         delete p;
         return LDP_ERR_UNSUPPORTED;

@@ -144,43 +144,11 @@ __device__ __forceinline__ void make_row(Row &r, uint32_t u0, uint32_t u1, uint3
 }
 
 // Raw words of one row: 16 bytes starting at the 4-aligned offset at or
-// below the lane's first byte, plus the shift s (0..3) to the first byte.
+// below the lane's first byte, plus the shift s (0..3) to that byte.
 struct RawRow {
     uint32_t w[4];
     uint32_t s;
 };
-
-template <bool ALIGNED>
-__device__ __forceinline__ void load_row(RawRow &rr, __amdgpu_buffer_rsrc_t rsrc, uint32_t off)
-{
-    if constexpr (ALIGNED) {
-        rr.s = 0;
-        rr.w[0] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)off, 0, 0);
-        rr.w[1] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)(off + 4), 0, 0);
-        rr.w[2] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)(off + 8), 0, 0);
-        rr.w[3] = 0;
-    } else {
-        rr.s = off & 3u;
-        uint32_t a = off & ~3u;
-        rr.w[0] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)a, 0, 0);
-        rr.w[1] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)(a + 4), 0, 0);
-        rr.w[2] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)(a + 8), 0, 0);
-        rr.w[3] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)(a + 12), 0, 0);
-    }
-}
-
-template <bool ALIGNED>
-__device__ __forceinline__ void unpack_row(Row &r, const RawRow &rr)
-{
-    if constexpr (ALIGNED) {
-        make_row(r, rr.w[0], rr.w[1], rr.w[2]);
-    } else {
-        uint32_t u0 = __builtin_amdgcn_alignbyte(rr.w[1], rr.w[0], rr.s);
-        uint32_t u1 = __builtin_amdgcn_alignbyte(rr.w[2], rr.w[1], rr.s);
-        uint32_t u2 = __builtin_amdgcn_alignbyte(rr.w[3], rr.w[2], rr.s);
-        make_row(r, u0, u1, u2);
-    }
-}
 
 // ------------------------------------------------------------ one code row
 // Codes of the lane's 8 pixels for the code row whose image rows are t
@@ -201,44 +169,47 @@ __device__ __forceinline__ void code_row(const Row &t, const Row &b, const uint3
         for (int a = 0; a < 6; ++a)
             col[a] = Vt[a] + b.X[a];
 
-        uint32_t d[4][8];
+        // Two halves: pixel pairs (0, 1) give the codes of pixels 0, 1, 4, 5;
+        // pairs (2, 3) those of pixels 2, 3, 6, 7.  Each direction's sign
+        // bits are folded into the code as soon as they exist, which keeps
+        // few values live.
+        uint32_t code[2];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int a = c + 1;
-            uint32_t S[8];
-            S[0] = col[a + 1];           // E   column to the right
-            S[1] = Vt[a + 1] + t.X[a];   // NE  E + NE + N
-            S[2] = t.R[c];               // N   row above
-            S[3] = Vt[a - 1] + t.X[a];   // NW  N + NW + W
-            S[4] = col[a - 1];           // W   column to the left
-            S[5] = Vb[a - 1] + b.X[a];   // SW  W + SW + S
-            S[6] = b.R[c];               // S   row below
-            S[7] = Vb[a + 1] + b.X[a];   // SE  S + SE + E
-            u16x2 Sv[8];
+        for (int h = 0; h < 2; ++h) {
+            uint32_t S[2][8], bias[2];
 #pragma unroll
-            for (int i = 0; i < 8; ++i)
-                Sv[i] = V(S[i]);
-            const uint32_t thr = U(kth_largest<K>(Sv));
-            const uint32_t bias = 0x80008000u - thr;  // 0x8000 - thr per field
+            for (int e = 0; e < 2; ++e) {
+                const int c = 2 * h + e, a = c + 1;
+                S[e][0] = col[a + 1];           // E   column to the right
+                S[e][1] = Vt[a + 1] + t.X[a];   // NE  E + NE + N
+                S[e][2] = t.R[c];               // N   row above
+                S[e][3] = Vt[a - 1] + t.X[a];   // NW  N + NW + W
+                S[e][4] = col[a - 1];           // W   column to the left
+                S[e][5] = Vb[a - 1] + b.X[a];   // SW  W + SW + S
+                S[e][6] = b.R[c];               // S   row below
+                S[e][7] = Vb[a + 1] + b.X[a];   // SE  S + SE + E
+                u16x2 Sv[8];
 #pragma unroll
-            for (int i = 0; i < 8; ++i)
-                d[c][i] = S[i] + bias;  // bit 15 of a field set iff S_i >= thr
+                for (int i = 0; i < 8; ++i)
+                    Sv[i] = V(S[e][i]);
+                bias[e] = 0x80008000u - U(kth_largest<K>(Sv));  // 0x8000 - thr per field
+            }
+            // bit 15 of a field of S_i + bias is set iff S_i >= thr; v_perm_b32
+            // turns the four sign bits of a direction into byte masks
+            // [first pair lo, second pair lo, first hi, second hi], and bit i of
+            // every byte is taken from direction i.
+            uint32_t acc = __builtin_amdgcn_perm(S[1][0] + bias[1], S[0][0] + bias[0], 0x0B090A08u);
+#pragma unroll
+            for (int i = 1; i < 8; ++i) {
+                const uint32_t msk = __builtin_amdgcn_perm(S[1][i] + bias[1], S[0][i] + bias[0],
+                                                           0x0B090A08u);
+                acc = __builtin_amdgcn_bitop3_b32(0x01010101u << i, msk, acc, 0xCA);
+            }
+            code[h] = acc;
         }
-        // Byte masks: M01 = [px0, px1, px4, px5], M23 = [px2, px3, px6, px7],
-        // 0xFF where S_i >= thr (the sign selectors 8..11 of v_perm_b32),
-        // merged bit by bit: bit i of every byte from direction i.
-        uint32_t c01 = __builtin_amdgcn_perm(d[1][0], d[0][0], 0x0B090A08u);
-        uint32_t c23 = __builtin_amdgcn_perm(d[3][0], d[2][0], 0x0B090A08u);
-#pragma unroll
-        for (int i = 1; i < 8; ++i) {
-            const uint32_t m = 0x01010101u << i;
-            uint32_t m01 = __builtin_amdgcn_perm(d[1][i], d[0][i], 0x0B090A08u);
-            uint32_t m23 = __builtin_amdgcn_perm(d[3][i], d[2][i], 0x0B090A08u);
-            c01 = __builtin_amdgcn_bitop3_b32(m, m01, c01, 0xCA);  // m ? m01 : c01
-            c23 = __builtin_amdgcn_bitop3_b32(m, m23, c23, 0xCA);
-        }
-        lo = __builtin_amdgcn_perm(c23, c01, 0x05040100u);
-        hi = __builtin_amdgcn_perm(c23, c01, 0x07060302u);
+        // code[0] = [px0, px1, px4, px5], code[1] = [px2, px3, px6, px7]
+        lo = __builtin_amdgcn_perm(code[1], code[0], 0x05040100u);
+        hi = __builtin_amdgcn_perm(code[1], code[0], 0x07060302u);
     }
 }
 

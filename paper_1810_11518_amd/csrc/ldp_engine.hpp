@@ -1,24 +1,30 @@
 // ldp_engine.hpp -- the per-lane row walk shared by every LDP kernel.
 //
-// A task is one column group (8 code columns) of one image over a range of
-// code rows.  The lane keeps the three image rows around the current code
-// row in registers, loads each new row once (prefetched one row ahead) with
-// hardware bounds-checked buffer loads, computes the 8 codes, and hands them
-// to the store and/or the LDS histogram.
+// A task is one column group (8 adjacent code columns) of one image over a
+// range of code rows that lies inside one cell row.  The lane keeps the three
+// image rows around the current code row in registers, loads each new row
+// once (prefetched one row ahead) with hardware bounds-checked buffer loads,
+// computes the 8 codes, stores them and counts them in the LDS histogram.
+//
+// Every lane owns 8 code columns: the last group of a row is moved left so
+// that it ends at the last column (it recomputes, and stores again with the
+// same values, the columns it shares with the previous group; its first
+// 8 - n columns go to a discard bin of the histogram so every pixel is
+// counted once).  Only code maps narrower than 8 columns take a masked path.
 #pragma once
 #include "ldp_device.hpp"
 
 namespace ldp {
 
 // An image as the kernels see it.  `off0` is the image start relative to the
-// 4-aligned base address in the buffer descriptor.
+// 4-aligned base address in the image's buffer descriptor.
 struct ImgView {
-    __amdgpu_buffer_rsrc_t rsrc;
+    __amdgpu_buffer_rsrc_t rsrc;   // image bytes
+    __amdgpu_buffer_rsrc_t crsrc;  // code map bytes
     uint32_t off0;
-    int64_t stride;
-    int32_t H, W;      // image
-    int32_t Hc, Wc;    // code map
-    uint8_t *codes;    // may be null
+    uint32_t stride;
+    int32_t H, W;    // image
+    int32_t Hc, Wc;  // code map
 };
 
 __device__ __forceinline__ ImgView make_view(const uint8_t *img, int64_t stride, int32_t H,
@@ -31,19 +37,15 @@ __device__ __forceinline__ ImgView make_view(const uint8_t *img, int64_t stride,
     int64_t extent = (int64_t)v.off0 + (int64_t)(H - 1) * stride + W;
     uint32_t nrec = (uint32_t)((extent + 3) & ~(int64_t)3);
     v.rsrc = __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, (int)nrec, 0x00020000);
-    v.stride = stride;
+    v.stride = (uint32_t)stride;
     v.H = H;
     v.W = W;
     v.Hc = H - 2;
     v.Wc = W - 2;
-    v.codes = codes;
+    // the range check of the descriptor keeps every store inside the map
+    int64_t csize = codes ? (int64_t)v.Hc * v.Wc : 0;
+    v.crsrc = __builtin_amdgcn_make_buffer_rsrc((void *)codes, (short)0, (int)csize, 0x00020000);
     return v;
-}
-
-// Rows start on 4-byte boundaries: the lane's dwords need no realignment.
-__device__ __forceinline__ bool image_aligned_dev(const uint8_t *img, int64_t stride)
-{
-    return ((uintptr_t)img & 3u) == 0 && (stride & 3) == 0;
 }
 
 // First code row (column) of cell `c` in a floor partition of n rows into
@@ -53,120 +55,177 @@ __host__ __device__ __forceinline__ int32_t cell_start(int32_t c, int32_t n, int
     return (int32_t)(((int64_t)c * n + cells - 1) / cells);
 }
 
-__device__ __forceinline__ void store8(uint8_t *p, uint32_t lo, uint32_t hi, int nvalid)
+// LDS histogram window: cell rows [cy0, cy0 + ncy) x cells_x cells of 256
+// uint32 bins at byte ((cy - cy0)*cells_x + cx)*1024, then one discard cell.
+struct HistWin {
+    uint32_t *lds;
+    int32_t cells_y, cells_x;
+    int32_t cy0, ncy;
+    __device__ uint32_t discard() const { return (uint32_t)(ncy * cells_x) * 1024u; }
+};
+
+// Loads one image row for the lane: 16 bytes from the 4-aligned offset at or
+// below the lane's first byte (aligned dwords never leave the image's last
+// page), then realigns them.
+__device__ __forceinline__ void load_raw(RawRow &rr, __amdgpu_buffer_rsrc_t rsrc, uint32_t off)
 {
-    if (nvalid >= 8) {
-        uint32_t a = (uint32_t)(uintptr_t)p & 3u;
-        if (a == 0) {
-            reinterpret_cast<uint32_t *>(p)[0] = lo;
-            reinterpret_cast<uint32_t *>(p)[1] = hi;
-        } else if (a == 2) {
-            reinterpret_cast<uint16_t *>(p)[0] = (uint16_t)lo;
-            reinterpret_cast<uint16_t *>(p)[1] = (uint16_t)(lo >> 16);
-            reinterpret_cast<uint16_t *>(p)[2] = (uint16_t)hi;
-            reinterpret_cast<uint16_t *>(p)[3] = (uint16_t)(hi >> 16);
+    rr.s = off & 3u;
+    const uint32_t a = off & ~3u;
+    rr.w[0] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)a, 0, 0);
+    rr.w[1] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)(a + 4), 0, 0);
+    rr.w[2] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)(a + 8), 0, 0);
+    rr.w[3] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)(a + 12), 0, 0);
+}
+
+__device__ __forceinline__ void unpack_raw(Row &r, const RawRow &rr)
+{
+    uint32_t u0 = __builtin_amdgcn_alignbyte(rr.w[1], rr.w[0], rr.s);
+    uint32_t u1 = __builtin_amdgcn_alignbyte(rr.w[2], rr.w[1], rr.s);
+    uint32_t u2 = __builtin_amdgcn_alignbyte(rr.w[3], rr.w[2], rr.s);
+    make_row(r, u0, u1, u2);
+}
+
+// Per-task state of the row walk.
+struct Walk {
+    uint32_t off, last_off;  // image byte offset of the prefetched / last row
+    uint32_t coff;           // code byte offset of the current code row
+    uint32_t cb[8];          // histogram byte base of each pixel's cell
+    bool uniform_cell;       // all 8 pixels counted in one cell
+};
+
+// One code row: the next image row arrives in `raw` and becomes `b`; t and m
+// are the two rows above; Vt = X_t + X_m.  Writes Vb = X_m + X_b.
+template <int K, bool HIST, bool CODES>
+__device__ __forceinline__ void step(const ImgView &im, const HistWin &hw, Walk &w, RawRow &raw,
+                                     const Row &t, const Row &m, Row &b, const uint32_t (&Vt)[6],
+                                     uint32_t (&Vb)[6])
+{
+    unpack_raw(b, raw);
+    w.off = min(w.off + im.stride, w.last_off);
+    load_raw(raw, im.rsrc, w.off);  // prefetch the row after (clamped to the last)
+#pragma unroll
+    for (int a = 0; a < 6; ++a)
+        Vb[a] = m.X[a] + b.X[a];
+    uint32_t lo, hi;
+    code_row<K>(t, b, Vt, Vb, lo, hi);
+    if constexpr (CODES) {
+        // dword stores at any byte offset (the target allows unaligned access)
+        __builtin_amdgcn_raw_buffer_store_b32(lo, im.crsrc, (int)w.coff, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(hi, im.crsrc, (int)(w.coff + 4), 0, 0);
+        w.coff += (uint32_t)im.Wc;
+    }
+    if constexpr (HIST) {
+        char *lds = reinterpret_cast<char *>(hw.lds);
+        if (w.uniform_cell && lo == hi && lo == __builtin_amdgcn_alignbyte(lo, lo, 1)) {
+            // eight equal codes in one cell (flat regions): one update
+            atomicAdd(reinterpret_cast<uint32_t *>(lds + (w.cb[0] | ((lo & 0xFFu) << 2))), 8u);
         } else {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                p[q] = (uint8_t)(lo >> (8 * q));
-                p[4 + q] = (uint8_t)(hi >> (8 * q));
+            for (int p = 0; p < 8; ++p) {
+                const uint32_t x = p < 4 ? lo : hi;
+                const int q = p & 3;
+                const uint32_t sh = q == 0 ? (x << 2) : (x >> (8 * q - 2));
+                // (sh & 0x3FC) | cb[p]: cell bases are multiples of 1024
+                const uint32_t addr = __builtin_amdgcn_bitop3_b32(sh, 0x3FCu, w.cb[p], 0xEA);
+                atomicAdd(reinterpret_cast<uint32_t *>(lds + addr), 1u);
             }
-        }
-    } else {
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            if (q < nvalid)
-                p[q] = (uint8_t)((q < 4 ? lo : hi) >> (8 * (q & 3)));
         }
     }
 }
 
-// LDS histogram window of a task: cell rows [cy0, cy0 + ncy) x all cells_x
-// cell columns, 256 uint32 bins each, at lds[((cy - cy0)*cells_x + cx)*256].
-struct HistWin {
-    uint32_t *lds;
-    int32_t cells_y, cells_x;
-    int32_t cy0;
-};
-
-template <int K, bool ALIGNED, bool HIST>
+// Run the code rows [r0, r1) of column group g; they all lie in cell row cy.
+template <int K, bool HIST, bool CODES>
 __device__ __forceinline__ void run_task(const ImgView &im, const HistWin &hw, int32_t g,
-                                         int32_t r0, int32_t r1)
+                                         int32_t r0, int32_t r1, int32_t cy)
 {
-    const int32_t j0 = 8 * g;              // first code column of the lane
-    const int nvalid = min(8, im.Wc - j0); // pixels of the lane inside the map
-    uint32_t off = im.off0 + (uint32_t)((int64_t)r0 * im.stride) + (uint32_t)j0;
-    const uint32_t ostride = (uint32_t)im.stride;
-
-    // histogram addressing: byte offset of each pixel's cell in the window
-    uint32_t colb[8];
-    int32_t cyr = 0, next_cy_row = 0;
-    uint32_t rowb = 0;
+    // first code column of the lane: groups of 8, the last one ends at Wc - 1
+    const int32_t j0 = min(8 * g, im.Wc - 8);
+    const int32_t skip = 8 * g - j0;  // leading columns the previous group counts
+    Walk w;
+    w.off = im.off0 + (uint32_t)r0 * im.stride + (uint32_t)j0;
+    w.last_off = im.off0 + (uint32_t)(im.H - 1) * im.stride + (uint32_t)j0;
+    w.coff = (uint32_t)r0 * (uint32_t)im.Wc + (uint32_t)j0;
     if constexpr (HIST) {
+        const uint32_t rowb = (uint32_t)((cy - hw.cy0) * hw.cells_x) * 1024u;
 #pragma unroll
         for (int p = 0; p < 8; ++p) {
-            int32_t j = min(j0 + p, im.Wc - 1);
-            colb[p] = (uint32_t)(((int64_t)j * hw.cells_x) / im.Wc) * 1024u;
+            uint32_t cx = (uint32_t)(((int64_t)(j0 + p) * hw.cells_x) / im.Wc);
+            w.cb[p] = p < skip ? hw.discard() : rowb + cx * 1024u;
         }
-        cyr = (int32_t)(((int64_t)r0 * hw.cells_y) / im.Hc);
-        next_cy_row = cell_start(cyr + 1, im.Hc, hw.cells_y);
-        rowb = (uint32_t)((cyr - hw.cy0) * hw.cells_x) * 1024u;
+        w.uniform_cell = skip == 0 && w.cb[0] == w.cb[7];
     }
-    const bool one_cell = HIST && nvalid >= 8 && colb[0] == colb[7];
+    RawRow raw;
+    Row A, B, C;
+    uint32_t VAB[6], VBC[6], VCA[6];
+    load_raw(raw, im.rsrc, w.off);
+    unpack_raw(A, raw);
+    w.off += im.stride;
+    load_raw(raw, im.rsrc, w.off);
+    unpack_raw(B, raw);
+    w.off += im.stride;
+    load_raw(raw, im.rsrc, w.off);
+#pragma unroll
+    for (int a = 0; a < 6; ++a)
+        VAB[a] = A.X[a] + B.X[a];
+    // the three rows rotate through A, B, C (and the vertical pair sums
+    // through VAB, VBC, VCA) so no registers are copied between rows
+    int32_t n = r1 - r0;
+    for (; n >= 3; n -= 3) {
+        step<K, HIST, CODES>(im, hw, w, raw, A, B, C, VAB, VBC);
+        step<K, HIST, CODES>(im, hw, w, raw, B, C, A, VBC, VCA);
+        step<K, HIST, CODES>(im, hw, w, raw, C, A, B, VCA, VAB);
+    }
+    if (n >= 1)
+        step<K, HIST, CODES>(im, hw, w, raw, A, B, C, VAB, VBC);
+    if (n >= 2)
+        step<K, HIST, CODES>(im, hw, w, raw, B, C, A, VBC, VCA);
+}
 
+// Code rows [r0, r1) of a code map narrower than 8 columns: one lane, the
+// pixels past the map masked.
+template <int K, bool HIST, bool CODES>
+__device__ void run_task_narrow(const ImgView &im, const HistWin &hw, int32_t r0, int32_t r1,
+                                int32_t cy)
+{
+    const int nvalid = im.Wc;
+    const uint32_t off = im.off0 + (uint32_t)r0 * im.stride;
     RawRow raw;
     Row t, m, b;
-    load_row<ALIGNED>(raw, im.rsrc, off);
-    unpack_row<ALIGNED>(t, raw);
-    load_row<ALIGNED>(raw, im.rsrc, off + ostride);
-    unpack_row<ALIGNED>(m, raw);
-    load_row<ALIGNED>(raw, im.rsrc, off + 2 * ostride);
-    uint32_t Vt[6];
+    load_raw(raw, im.rsrc, off);
+    unpack_raw(t, raw);
+    load_raw(raw, im.rsrc, off + im.stride);
+    unpack_raw(m, raw);
+    uint32_t Vt[6], Vb[6];
 #pragma unroll
     for (int a = 0; a < 6; ++a)
         Vt[a] = t.X[a] + m.X[a];
-
-    uint8_t *cp = im.codes ? im.codes + (int64_t)r0 * im.Wc + j0 : nullptr;
+    uint32_t cb[8];
+    if constexpr (HIST) {
+        const uint32_t rowb = (uint32_t)((cy - hw.cy0) * hw.cells_x) * 1024u;
+        for (int p = 0; p < 8; ++p) {
+            uint32_t cx = (uint32_t)(((int64_t)min(p, im.Wc - 1) * hw.cells_x) / im.Wc);
+            cb[p] = p < nvalid ? rowb + cx * 1024u : hw.discard();
+        }
+    }
     for (int32_t r = r0; r < r1; ++r) {
-        unpack_row<ALIGNED>(b, raw);
-        // prefetch the next image row (clamped to the last row)
-        uint32_t noff = off + (uint32_t)(min(r + 3, im.H - 1) - r0) * ostride;
-        load_row<ALIGNED>(raw, im.rsrc, noff);
-
-        uint32_t Vb[6];
+        load_raw(raw, im.rsrc, off + (uint32_t)(r + 2 - r0) * im.stride);
+        unpack_raw(b, raw);
 #pragma unroll
         for (int a = 0; a < 6; ++a)
             Vb[a] = m.X[a] + b.X[a];
         uint32_t lo, hi;
         code_row<K>(t, b, Vt, Vb, lo, hi);
-
-        if (cp) {
-            store8(cp, lo, hi, nvalid);
-            cp += im.Wc;
+        if constexpr (CODES) {
+            const uint32_t coff = (uint32_t)r * (uint32_t)im.Wc;
+            for (int p = 0; p < nvalid; ++p)
+                __builtin_amdgcn_raw_buffer_store_b8((uint8_t)((p < 4 ? lo : hi) >> (8 * (p & 3))),
+                                                     im.crsrc, (int)(coff + p), 0, 0);
         }
         if constexpr (HIST) {
-            if (r == next_cy_row) {
-                ++cyr;
-                next_cy_row = cell_start(cyr + 1, im.Hc, hw.cells_y);
-                rowb = (uint32_t)((cyr - hw.cy0) * hw.cells_x) * 1024u;
-            }
-            // byte address of bin `code` of pixel p's cell: cell offsets are
-            // multiples of 1024, so (code << 2) is OR-ed in (v_bitop3_b32)
             char *lds = reinterpret_cast<char *>(hw.lds);
-            if (one_cell && lo == hi && lo == __builtin_amdgcn_alignbyte(lo, lo, 1)) {
-                // eight equal codes in one cell (flat regions): one update
-                const uint32_t addr = (rowb + colb[0]) | ((lo & 0xFFu) << 2);
-                atomicAdd(reinterpret_cast<uint32_t *>(lds + addr), 8u);
-            } else {
-#pragma unroll
-                for (int p = 0; p < 8; ++p) {
-                    const uint32_t w = p < 4 ? lo : hi;
-                    const int q = p & 3;
-                    const uint32_t sh = q == 0 ? (w << 2) : (w >> (8 * q - 2));
-                    const uint32_t addr = __builtin_amdgcn_bitop3_b32(sh, 0x3FCu, rowb + colb[p], 0xEA);
-                    if (nvalid >= 8 || p < nvalid)
-                        atomicAdd(reinterpret_cast<uint32_t *>(lds + addr), 1u);
-                }
+            for (int p = 0; p < 8; ++p) {
+                const uint32_t code = ((p < 4 ? lo : hi) >> (8 * (p & 3))) & 0xFFu;
+                atomicAdd(reinterpret_cast<uint32_t *>(lds + (cb[p] | (code << 2))), 1u);
             }
         }
         t = m;
@@ -177,11 +236,46 @@ __device__ __forceinline__ void run_task(const ImgView &im, const HistWin &hw, i
     }
 }
 
+// Split the code rows [r0, r1) of cell row cy among the workgroup's threads:
+// task = (row sub-band, column group).
+template <int K, bool HIST, bool CODES>
+__device__ __forceinline__ void run_rows(const ImgView &im, const HistWin &hw, int32_t r0,
+                                         int32_t r1, int32_t cy, int32_t min_task_rows)
+{
+    const int tid = threadIdx.x, nthreads = blockDim.x;
+    const int32_t nr = r1 - r0;
+    if (nr <= 0)
+        return;
+    if (im.Wc < 8) {
+        const int32_t nsub = min(nthreads, nr);
+        if (tid < nsub) {
+            const int32_t a0 = r0 + (int32_t)((int64_t)nr * tid / nsub);
+            const int32_t a1 = r0 + (int32_t)((int64_t)nr * (tid + 1) / nsub);
+            if (a1 > a0)
+                run_task_narrow<K, HIST, CODES>(im, hw, a0, a1, cy);
+        }
+        return;
+    }
+    const int32_t ngroups = (im.Wc + 7) / 8;
+    // row sub-bands per column group: as many as the threads allow, but no
+    // shorter than min_task_rows code rows
+    const int32_t nsub =
+        max(1, min(nthreads / ngroups, (nr + min_task_rows - 1) / min_task_rows));
+    const int32_t ntasks = ngroups * nsub;
+    for (int32_t task = tid; task < ntasks; task += nthreads) {
+        const int32_t g = task % ngroups, sb = task / ngroups;
+        const int32_t a0 = r0 + (int32_t)((int64_t)nr * sb / nsub);
+        const int32_t a1 = r0 + (int32_t)((int64_t)nr * (sb + 1) / nsub);
+        if (a1 > a0)
+            run_task<K, HIST, CODES>(im, hw, g, a0, a1, cy);
+    }
+}
+
 // ---------------------------------------------------------------- work items
-// One workgroup per work item of one image: the code rows [r0, r1) of cell
-// rows [cy0, cy1) (r0/r1 may cut a cell row when `split` > 1, and the
-// histogram flush then adds atomically into a zeroed array).
-template <int K, bool ALIGNED>
+// One workgroup per work item: code rows [r0, r1) of cell rows [cy0, cy1).
+// When r0/r1 cut a cell row (an image split across workgroups) the flush adds
+// atomically into a zeroed histogram; otherwise it stores.
+template <int K, bool CODES>
 __device__ __forceinline__ void fused_item(const ImgView &im, uint32_t *lds, int32_t cells_y,
                                            int32_t cells_x, int32_t cy0, int32_t cy1, int32_t r0,
                                            int32_t r1, uint32_t *hist, bool atomic_flush,
@@ -189,27 +283,19 @@ __device__ __forceinline__ void fused_item(const ImgView &im, uint32_t *lds, int
 {
     const int tid = threadIdx.x, nthreads = blockDim.x;
     const int32_t nbins = (cy1 - cy0) * cells_x * 256;
-    for (int32_t i = tid; i < nbins; i += nthreads)
+    for (int32_t i = tid; i < nbins + 256; i += nthreads)
         lds[i] = 0;
     __syncthreads();
-    const int32_t ngroups = (im.Wc + 7) / 8;
-    const int32_t nr = r1 - r0;
-    // row sub-bands per column group: as many as the threads allow, but no
-    // shorter than min_task_rows code rows
-    int32_t nsub = max(1, min(nthreads / ngroups, (nr + min_task_rows - 1) / min_task_rows));
-    const int32_t ntasks = ngroups * nsub;
-    HistWin hw{lds, cells_y, cells_x, cy0};
-    for (int32_t task = tid; task < ntasks; task += nthreads) {
-        int32_t g = task % ngroups, sb = task / ngroups;
-        int32_t a0 = r0 + (int32_t)((int64_t)nr * sb / nsub);
-        int32_t a1 = r0 + (int32_t)((int64_t)nr * (sb + 1) / nsub);
-        if (a1 > a0)
-            run_task<K, ALIGNED, true>(im, hw, g, a0, a1);
+    const HistWin hw{lds, cells_y, cells_x, cy0, cy1 - cy0};
+    for (int32_t cy = cy0; cy < cy1; ++cy) {
+        const int32_t a0 = max(r0, cell_start(cy, im.Hc, cells_y));
+        const int32_t a1 = min(r1, cell_start(cy + 1, im.Hc, cells_y));
+        run_rows<K, true, CODES>(im, hw, a0, a1, cy, min_task_rows);
     }
     __syncthreads();
     uint32_t *dst = hist + (int64_t)cy0 * cells_x * 256;
     for (int32_t i = tid; i < nbins; i += nthreads) {
-        uint32_t v = lds[i];
+        const uint32_t v = lds[i];
         if (!atomic_flush)
             dst[i] = v;
         else if (v)

@@ -29,10 +29,10 @@ inline int check_cells(int32_t H, int32_t W, int32_t cells_y, int32_t cells_x)
     return LDP_OK;
 }
 
-// Largest cells_x the fused kernels keep in LDS (one cell row, 1 KiB per cell).
-constexpr int32_t kMaxFusedCellsX = 64;
+// Largest cells_x the fused kernels keep in LDS (one cell row, 1 KiB per
+// cell, plus a discard cell).
+constexpr int32_t kMaxFusedCellsX = 63;
 
-bool image_aligned(const uint8_t *img, int64_t stride);
 int launch_codes(const uint8_t *img, int32_t H, int32_t W, int64_t stride, int32_t k,
                  uint8_t *codes, hipStream_t s);
 int launch_histograms(const uint8_t *codes, int32_t H, int32_t W, int32_t cells_y,

@@ -17,8 +17,12 @@ namespace ldp {
 
 // ---------------------------------------------------------------- codes
 // One thread per task: task = (row band, column group).
-template <int K, bool ALIGNED>
-__global__ void __launch_bounds__(256) codes_kernel(const uint8_t *__restrict__ img,
+#ifndef LDP_CODES_ATTR
+#define LDP_CODES_ATTR
+#endif
+
+template <int K>
+__global__ void __launch_bounds__(256) LDP_CODES_ATTR codes_kernel(const uint8_t *__restrict__ img,
                                                     int64_t stride, int32_t H, int32_t W,
                                                     uint8_t *__restrict__ codes, int32_t band_rows,
                                                     int32_t ngroups, int32_t ntasks)
@@ -26,13 +30,16 @@ __global__ void __launch_bounds__(256) codes_kernel(const uint8_t *__restrict__ 
     int32_t task = blockIdx.x * blockDim.x + threadIdx.x;
     if (task >= ntasks)
         return;
-    ImgView im = make_view(img, stride, H, W, codes);
-    int32_t g = task % ngroups;
-    int32_t band = task / ngroups;
-    int32_t r0 = band * band_rows;
-    int32_t r1 = min(r0 + band_rows, im.Hc);
-    HistWin hw{};
-    run_task<K, ALIGNED, false>(im, hw, g, r0, r1);
+    const ImgView im = make_view(img, stride, H, W, codes);
+    const int32_t g = task % ngroups;
+    const int32_t band = task / ngroups;
+    const int32_t r0 = band * band_rows;
+    const int32_t r1 = min(r0 + band_rows, im.Hc);
+    const HistWin hw{};
+    if (im.Wc < 8)
+        run_task_narrow<K, false, true>(im, hw, r0, r1, 0);
+    else
+        run_task<K, false, true>(im, hw, g, r0, r1, 0);
 }
 
 // ---------------------------------------------------------------- histograms
@@ -78,7 +85,7 @@ __global__ void zero_kernel(uint32_t *__restrict__ p, int64_t n)
 }
 
 // ---------------------------------------------------------------- fused
-template <int K, bool ALIGNED>
+template <int K, bool CODES>
 __global__ void __launch_bounds__(1024) fused_kernel(const uint8_t *__restrict__ img,
                                                      int64_t stride, int32_t H, int32_t W,
                                                      uint8_t *codes, uint32_t *hist,
@@ -86,22 +93,22 @@ __global__ void __launch_bounds__(1024) fused_kernel(const uint8_t *__restrict__
                                                      int32_t split)
 {
     extern __shared__ uint32_t lds[];
-    ImgView im = make_view(img, stride, H, W, codes);
+    const ImgView im = make_view(img, stride, H, W, codes);
     const int32_t cy = blockIdx.x / split, sp = blockIdx.x % split;
     const int32_t ry0 = cell_start(cy, im.Hc, cells_y), ry1 = cell_start(cy + 1, im.Hc, cells_y);
     const int32_t r0 = ry0 + (int32_t)((int64_t)(ry1 - ry0) * sp / split);
     const int32_t r1 = ry0 + (int32_t)((int64_t)(ry1 - ry0) * (sp + 1) / split);
-    fused_item<K, ALIGNED>(im, lds, cells_y, cells_x, cy, cy + 1, r0, r1, hist, split > 1, 4);
+    fused_item<K, CODES>(im, lds, cells_y, cells_x, cy, cy + 1, r0, r1, hist, split > 1, 4);
 }
 
 // ---------------------------------------------------------------- dispatch
 template <template <int, bool> class F, typename... Args>
-static hipError_t dispatch_k(int k, bool aligned, Args &&...args)
+static hipError_t dispatch_k(int k, bool flag, Args &&...args)
 {
     switch (k) {
 #define LDP_CASE(KK)                                                           \
     case KK:                                                                   \
-        return aligned ? F<KK, true>::launch(args...) : F<KK, false>::launch(args...);
+        return flag ? F<KK, true>::launch(args...) : F<KK, false>::launch(args...);
         LDP_CASE(1) LDP_CASE(2) LDP_CASE(3) LDP_CASE(4)
         LDP_CASE(5) LDP_CASE(6) LDP_CASE(7) LDP_CASE(8)
 #undef LDP_CASE
@@ -109,34 +116,29 @@ static hipError_t dispatch_k(int k, bool aligned, Args &&...args)
     return hipErrorInvalidValue;
 }
 
-template <int K, bool AL>
+template <int K, bool UNUSED>
 struct CodesLaunch {
     static hipError_t launch(dim3 grid, dim3 block, hipStream_t s, const uint8_t *img,
                              int64_t stride, int32_t H, int32_t W, uint8_t *codes, int32_t band,
                              int32_t ngroups, int32_t ntasks)
     {
-        hipLaunchKernelGGL((codes_kernel<K, AL>), grid, block, 0, s, img, stride, H, W, codes,
+        hipLaunchKernelGGL((codes_kernel<K>), grid, block, 0, s, img, stride, H, W, codes,
                            band, ngroups, ntasks);
         return hipGetLastError();
     }
 };
 
-template <int K, bool AL>
+template <int K, bool CODES>
 struct FusedLaunch {
     static hipError_t launch(dim3 grid, dim3 block, size_t lds, hipStream_t s, const uint8_t *img,
                              int64_t stride, int32_t H, int32_t W, uint8_t *codes,
                              uint32_t *hist, int32_t cells_y, int32_t cells_x, int32_t split)
     {
-        hipLaunchKernelGGL((fused_kernel<K, AL>), grid, block, lds, s, img, stride, H, W, codes,
+        hipLaunchKernelGGL((fused_kernel<K, CODES>), grid, block, lds, s, img, stride, H, W, codes,
                            hist, cells_y, cells_x, split);
         return hipGetLastError();
     }
 };
-
-bool image_aligned(const uint8_t *img, int64_t stride)
-{
-    return ((uintptr_t)img & 3u) == 0 && (stride & 3) == 0;
-}
 
 int launch_codes(const uint8_t *img, int32_t H, int32_t W, int64_t stride, int32_t k,
                  uint8_t *codes, hipStream_t s)
@@ -149,7 +151,7 @@ int launch_codes(const uint8_t *img, int32_t H, int32_t W, int64_t stride, int32
     int32_t nbands = (Hc + band - 1) / band;
     int32_t ntasks = ngroups * nbands;
     dim3 block(256), grid((ntasks + 255) / 256);
-    hipError_t e = dispatch_k<CodesLaunch>(k, image_aligned(img, stride), grid, block, s, img,
+    hipError_t e = dispatch_k<CodesLaunch>(k, true, grid, block, s, img,
                                            stride, H, W, codes, band, ngroups, ntasks);
     return e == hipSuccess ? LDP_OK : LDP_ERR_HIP;
 }
@@ -175,8 +177,8 @@ int launch_histograms(const uint8_t *codes, int32_t H, int32_t W, int32_t cells_
     return hipGetLastError() == hipSuccess ? LDP_OK : LDP_ERR_HIP;
 }
 
-// LDS bytes of one cell row of histograms
-static size_t fused_lds_bytes(int32_t cells_x) { return (size_t)cells_x * 256 * 4; }
+// LDS bytes of one cell row of histograms plus the discard cell
+static size_t fused_lds_bytes(int32_t cells_x) { return (size_t)(cells_x + 1) * 256 * 4; }
 
 int launch_extract(const uint8_t *img, int32_t H, int32_t W, int64_t stride, int32_t k,
                    int32_t cells_y, int32_t cells_x, uint8_t *codes, uint32_t *hist,
@@ -203,7 +205,7 @@ int launch_extract(const uint8_t *img, int32_t H, int32_t W, int64_t stride, int
                            dim3(256), 0, s, hist, n);
     }
     size_t lds = fused_lds_bytes(cells_x);
-    hipError_t e = dispatch_k<FusedLaunch>(k, image_aligned(img, stride),
+    hipError_t e = dispatch_k<FusedLaunch>(k, codes != nullptr,
                                            dim3(cells_y * split), dim3(threads), lds, s, img,
                                            stride, H, W, codes, hist, cells_y, cells_x, split);
     return e == hipSuccess ? LDP_OK : LDP_ERR_HIP;
