@@ -33,8 +33,15 @@ def parse():
     ap.add_argument("--plain-steps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-images", type=int, default=None)
-    ap.add_argument("--tune", default=None, help="JSON tune dict for the batch plan")
+    ap.add_argument("--tune", default=None, help="JSON tune dict for the batch plan (else the "
+                    "autotuner's cached choice for this batch, else defaults)")
+    ap.add_argument("--autotune", type=float, default=0.0, metavar="SECONDS",
+                    help="tune the batch plan on this batch for about SECONDS and cache it")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"))
+    ap.add_argument("--serve-rates", default="2000,10000",
+                    help="comma-separated Poisson arrival rates (images/s) for the serving "
+                         "run; empty to skip")
+    ap.add_argument("--serve-seconds", type=float, default=1.5)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (a kernel of "
                          "known traffic for scaling hardware byte counters)")
@@ -52,6 +59,63 @@ def algorithmic_bytes(Hs, Ws, cells):
     H = Hs.astype(np.int64)
     W = Ws.astype(np.int64)
     return int((H * W + (H - 2) * (W - 2)).sum() + len(H) * cells[0] * cells[1] * 1024)
+
+
+def serve_bench(binding, synth, rates, seconds, k=3, cells=(7, 6), pool_images=256):
+    """Open-loop serving run per rate: Poisson arrivals of single images with
+    sides log-uniform in [64, 2048] (drawn from a pool of pre-generated images),
+    histogram outputs; latency = results on the host - scheduled arrival."""
+    import torch
+    _, Hs, Ws = synth.serve_stream(1000, pool_images)
+    off, strides, total = synth.layout(Hs, Ws)
+    keep = torch.empty(total + 64, dtype=torch.uint8, pin_memory=True)
+    host = keep.numpy()
+    synth.fill(host, off, Hs, Ws, strides, synth.KIND_BLUR_RECTS, synth.SEEDS["serve"])
+    imgs = [host[int(o):int(o) + int(h) * int(st)].reshape(int(h), int(st))[:, :int(w)]
+            for o, h, w, st in zip(off, Hs, Ws, strides)]
+    nout = 2048
+    hb = cells[0] * cells[1] * 256
+    keep_out = torch.empty(nout * hb * 4, dtype=torch.uint8, pin_memory=True)
+    outs = keep_out.numpy().view(np.uint32).reshape(nout, hb)
+    results = []
+    for rate in rates:
+        n = max(1, int(rate * seconds))
+        arr, _, _ = synth.serve_stream(rate, n)
+        srv = binding.Server(4 << 30, max_inflight=1024, max_batch=256, depth=4, k=k,
+                             cells_y=cells[0], cells_x=cells[1])
+        t0 = binding.now() + 0.02
+        sched = t0 + arr
+        lat = np.zeros(n)
+        sizes = np.zeros(n)
+        i = done = 0
+        first = None
+        px = 0
+        while done < n:
+            now = binding.now()
+            while i < n and sched[i] <= now:
+                j = i % pool_images
+                rid = srv.submit(imgs[j], outs[i % nout])
+                if first is None:
+                    first = rid
+                px += int(Hs[j]) * int(Ws[j])
+                i += 1
+            for c in srv.poll(wait_us=0 if i < n else 2000):
+                lat[c["id"] - first] = c["t_done"] - sched[c["id"] - first]
+                sizes[c["id"] - first] = c["batch_size"]
+                done += 1
+                last_done = c["t_done"]
+        st = srv.stats()
+        srv.close()
+        span = last_done - t0
+        results.append({"rate_img_s": rate, "requests": n,
+                        "throughput_img_s": round(n / span, 1),
+                        "throughput_mpix_s": round(px / span / 1e6, 1),
+                        "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                        "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+                        "mean_batch": round(float(sizes.mean()), 1),
+                        "peak_batches_in_flight": st["peak_batches"],
+                        "launches": st["launches"]})
+    return results
 
 
 def main():
@@ -97,7 +161,17 @@ def main():
                                     [base_h + j * hb for j in range(n)],
                                     [int(s) for s in strides], [int(h) for h in Hs],
                                     [int(x) for x in Ws])
-    tune = json.loads(args.tune) if args.tune else None
+    from paper_1810_11518_amd import autotune
+    tune_src = "default"
+    if args.tune:
+        tune, tune_src = json.loads(args.tune), "command line"
+    elif args.autotune > 0:
+        tune, tms = autotune.tune_batch(descs, Hs, Ws, k, cells, budget_s=args.autotune)
+        autotune.save(Hs, Ws, k, cells, tune, tms, note="bench.py --workload %s" % args.workload)
+        tune_src = "autotuned now"
+    else:
+        tune = autotune.lookup(Hs, Ws, k, cells)
+        tune_src = "autotune cache" if tune else "default"
     pixels = int((Hs.astype(np.int64) * Ws).sum())
     plan = binding.BatchPlan(n, pixels, k, cells[0], cells[1], tune)
     plan.set(descs)
@@ -160,7 +234,8 @@ def main():
     cpu = None
     if not args.no_cpu:
         from oracle import native
-        ncpu = args.cpu_images or {"batch": 320, "uneven": 320, "large": 2}[args.workload]
+        # about 10 s of single-thread oracle work
+        ncpu = args.cpu_images or {"batch": 800, "uneven": 800, "large": 4}[args.workload]
         ncpu = min(ncpu, n)
         hv = host.numpy()
         t0 = time.perf_counter()
@@ -173,6 +248,14 @@ def main():
         cpu = {"value": round(px / dt / 1e6, 3), "unit": "Mpixel/s", "cores": 1, "kind": "oracle",
                "sample": "first %d of %d images, plain C oracle (direct masks, sort), "
                          "single thread, %.1f s" % (ncpu, n, dt)}
+
+    serve = None
+    if args.serve_rates:
+        rates = [int(x) for x in args.serve_rates.split(",") if x]
+        serve = {"workload": "Poisson arrivals, single uint8 images, sides log-uniform in "
+                             "[64,2048], k=3, 7x6 cells, histogram outputs; latency from "
+                             "scheduled arrival to results on the host",
+                 "runs": serve_bench(binding, synth, rates, args.serve_seconds)}
 
     desc = {"batch": "4096 x 490x640 uint8, blurred noise + 8 rectangles",
             "uneven": "10000 uint8 images, H and W uniform in [48,1024], blurred noise + rectangles",
@@ -193,7 +276,7 @@ def main():
         "config": {"workload": "%s: %s, k=%d, %dx%d cells" % (args.workload, desc[args.workload], k,
                                                               cells[0], cells[1]),
                    "images": n, "pixels": pixels, "k": k, "cells": list(cells),
-                   "work_items": items, "grid_blocks": grid},
+                   "work_items": items, "grid_blocks": grid, "tune": tune, "tune_source": tune_src},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "algorithmic_bytes_per_launch": abytes},
@@ -204,6 +287,7 @@ def main():
         "batched_over_plain": round(ms_plain / ms_step, 2) if ms_plain else None,
         "cpu_baseline": cpu,
         "checked_images_bit_exact": check,
+        "serve": serve,
         "gen_seconds": round(gen_s, 1),
     }
     print(json.dumps(out))

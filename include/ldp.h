@@ -114,13 +114,24 @@ typedef struct ldp_image_desc {
     int32_t H, W;       /* 3..LDP_MAX_SIDE */
 } ldp_image_desc;
 
-/* Launch shape of the batched kernel (chosen by the autotuner; zero fields
- * take defaults). */
-typedef struct ldp_tune {
+/* Launch shape and work split of the batched kernel, chosen by the autotuner
+ * (paper_1810_11518_amd/autotune.py); zero fields take defaults.  Images are
+ * put in the first size class whose max_pixels >= H*W (the last class takes
+ * the rest); a class fixes how many cell rows of an image one work item
+ * covers and how many code rows one lane task covers at least. */
+#define LDP_MAX_SIZE_CLASSES 4
+typedef struct ldp_size_class {
+    int64_t max_pixels;         /* upper bound of H*W for the class */
     int32_t cell_rows_per_item; /* cell rows of one image per work item, >= 1 */
-    int32_t block_threads;      /* threads per workgroup: 256, 512 or 1024 */
-    int32_t grid_blocks;        /* persistent workgroups; 0 = fill the device */
     int32_t rows_per_task;      /* target code rows per lane task, >= 1 */
+} ldp_size_class;
+
+typedef struct ldp_tune {
+    int32_t block_threads; /* threads per workgroup: 256, 512 or 1024 */
+    int32_t grid_blocks;   /* persistent workgroups; 0 = fill the device */
+    int32_t n_classes;     /* 0 (one default class) .. LDP_MAX_SIZE_CLASSES */
+    int32_t reserved;
+    ldp_size_class classes[LDP_MAX_SIZE_CLASSES];
 } ldp_tune;
 
 typedef struct ldp_batch_plan ldp_batch_plan;
@@ -160,6 +171,81 @@ int ldp_batch_plan_info(const ldp_batch_plan *plan, int64_t *work_items, int32_t
 
 /* ldp_batch_plan_destroy -- release the plan (waits for its device work). */
 int ldp_batch_plan_destroy(ldp_batch_plan *plan);
+
+/* ---------------------------------------------------------------- serving
+ *
+ * Continuous batching of single-image requests.  A request (a HOST image and
+ * HOST result buffers) is admitted when the server's device memory pool has
+ * room for its image, codes and histograms and a request slot is free;
+ * otherwise it waits, in arrival order.  A dispatcher thread copies admitted
+ * images to the device and launches them as one persistent batch (the
+ * descriptor and work tables and the work queue live on the device) on one
+ * of `depth` streams, so requests that arrive while earlier batches run are
+ * admitted as memory frees up and their work overlaps on the device.  When a
+ * batch's results are back on the host its memory and slots are released.
+ * Results are exactly those of ldp_extract on the image alone.
+ */
+typedef struct ldp_server ldp_server;
+
+typedef struct ldp_server_config {
+    int64_t pool_bytes;    /* device pool for images + codes + histograms */
+    int32_t max_inflight;  /* requests admitted at once (slots) */
+    int32_t max_batch;     /* requests per launch */
+    int32_t depth;         /* launches in flight at once (streams), 1..8 */
+    int32_t k;             /* 1..8 */
+    int32_t cells_y, cells_x;
+    int32_t dry_run;       /* 1: no device work at all (policy tests on a CPU):
+                            * admission and batching run, batches "complete"
+                            * dry_run_us microseconds after launch, outputs are
+                            * not written */
+    int32_t dry_run_us;
+} ldp_server_config;
+
+/* Completion record of a request; times are ldp_now() seconds. */
+typedef struct ldp_completion {
+    int64_t id;
+    double t_submit;  /* when ldp_server_submit accepted it */
+    double t_admit;   /* when it got device memory and a slot */
+    double t_done;    /* when the dispatcher saw its results on the host */
+    int32_t status;   /* LDP_OK or the error of its batch */
+    int32_t batch_size;
+} ldp_completion;
+
+typedef struct ldp_server_stats {
+    int64_t submitted, completed, rejected, launches;
+    int64_t peak_pool_bytes;  /* most pool bytes in use at once */
+    int32_t peak_inflight;    /* most requests admitted at once */
+    int32_t peak_batches;     /* most launches in flight at once */
+    int32_t max_batch_seen;
+    int32_t waiting;          /* requests waiting for admission now */
+} ldp_server_stats;
+
+/* Monotonic clock (seconds) used for every server timestamp. */
+double ldp_now(void);
+
+/* Create a server (allocates the pool, streams and batch plans; starts the
+ * dispatcher thread).  Errors: LDP_ERR_INVALID_ARG, LDP_ERR_NO_MEMORY,
+ * LDP_ERR_HIP. */
+int ldp_server_create(ldp_server **server, const ldp_server_config *config);
+
+/* Queue one request.  img is HOST memory, H x W with pitch `stride`; codes
+ * ((H-2)*(W-2) bytes, may be NULL) and hist (cells_y*cells_x*256 uint32) are
+ * HOST outputs written before the request completes.  All three buffers must
+ * stay valid until completion; page-locked memory gives asynchronous copies.
+ * Returns the request id in *id.  Errors: LDP_ERR_INVALID_ARG (bad sizes),
+ * LDP_ERR_NO_MEMORY (the request can never fit the pool: rejected). */
+int ldp_server_submit(ldp_server *server, const uint8_t *img, int32_t H, int32_t W,
+                      int64_t stride, uint8_t *codes, uint32_t *hist, int64_t *id);
+
+/* Completed requests since the last poll (up to max), waiting up to
+ * wait_us microseconds for at least one.  *n receives the count. */
+int ldp_server_poll(ldp_server *server, ldp_completion *out, int32_t max, int32_t *n,
+                    int32_t wait_us);
+
+int ldp_server_stats_get(ldp_server *server, ldp_server_stats *stats);
+
+/* Stop the dispatcher after the queued requests complete, release all. */
+int ldp_server_destroy(ldp_server *server);
 
 #ifdef __cplusplus
 }

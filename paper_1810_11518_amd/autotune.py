@@ -1,0 +1,140 @@
+"""Autotuner for the persistent batched launch.
+
+The batch plan (csrc/ldp_batch.hip) cuts every image into work items of whole
+cell rows and runs them on resident workgroups.  How that is done is a small
+set of choices (ldp_tune): the workgroup size, and per image size class the
+number of cell rows one work item covers and the minimum code rows of one
+lane task (short tasks give more parallelism inside an item, long ones
+amortise the three-row prologue of each task).  This module times candidate
+choices on the caller's own device-resident batch by coordinate descent and
+keeps the winners in a JSON cache keyed by GPU architecture, k, cell grid and
+a coarse signature of the image size distribution.
+"""
+import json
+import os
+import time
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+CACHE = os.path.join(_HERE, "tuned.json")
+
+THREADS = (256, 512, 1024)
+ROWS_PER_TASK = (4, 8, 16, 32)
+
+
+def arch():
+    import torch
+    name = torch.cuda.get_device_properties(0).gcnArchName
+    return name.split(":")[0]
+
+
+def size_signature(Hs, Ws):
+    """Coarse size-distribution signature: a single size, or pixel-count
+    quantiles rounded to powers of two."""
+    Hs = np.asarray(Hs)
+    Ws = np.asarray(Ws)
+    if len(Hs) and (Hs == Hs[0]).all() and (Ws == Ws[0]).all():
+        return "%dx%d" % (int(Hs[0]), int(Ws[0]))
+    px = Hs.astype(np.int64) * Ws
+    q = [int(2 ** round(np.log2(max(1, v)))) for v in np.quantile(px, [0.1, 0.5, 0.9])]
+    return "mix:%d/%d/%d" % tuple(q)
+
+
+def key(Hs, Ws, k, cells):
+    return "%s|k%d|%dx%d|%s" % (arch(), k, cells[0], cells[1], size_signature(Hs, Ws))
+
+
+def load_cache(path=CACHE):
+    if os.path.exists(path):
+        with open(path) as f:
+            return json.load(f)
+    return {}
+
+
+def lookup(Hs, Ws, k, cells, path=CACHE):
+    """Cached tune dict for this batch shape, or None."""
+    return load_cache(path).get(key(Hs, Ws, k, cells), {}).get("tune")
+
+
+def default_classes(Hs, Ws, cells_y):
+    """Size classes for a batch: one class for a single size, else small /
+    medium / large split at pixel-count quantiles."""
+    px = np.asarray(Hs, dtype=np.int64) * np.asarray(Ws, dtype=np.int64)
+    if len(px) == 0 or (px == px[0]).all():
+        return [dict(cell_rows_per_item=1, rows_per_task=8)]
+    b1, b2 = (int(v) for v in np.quantile(px, [1 / 3, 2 / 3]))
+    return [dict(max_pixels=b1, cell_rows_per_item=min(cells_y, 4), rows_per_task=4),
+            dict(max_pixels=b2, cell_rows_per_item=2, rows_per_task=8),
+            dict(cell_rows_per_item=1, rows_per_task=8)]
+
+
+def _time_plan(binding, descs, n, pixels, k, cells, tune, reps=5):
+    import torch
+    plan = binding.BatchPlan(n, pixels, k, cells[0], cells[1], tune)
+    try:
+        plan.set(descs)
+        for _ in range(2):
+            plan.run()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            plan.run()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+    finally:
+        plan.close()
+
+
+def tune_batch(descs, Hs, Ws, k, cells, budget_s=60.0, verbose=False):
+    """Coordinate descent over ldp_tune for the device-resident batch `descs`
+    (a ctypes ImageDesc array).  Returns (best tune dict, best ms)."""
+    from . import binding
+    n = len(descs)
+    pixels = int((np.asarray(Hs, dtype=np.int64) * np.asarray(Ws, dtype=np.int64)).sum())
+    t_end = time.time() + budget_s
+    best = dict(block_threads=256, classes=default_classes(Hs, Ws, cells[0]))
+    best_ms = _time_plan(binding, descs, n, pixels, k, cells, best)
+    seen = {json.dumps(best, sort_keys=True): best_ms}
+
+    def attempt(cand):
+        nonlocal best, best_ms
+        s = json.dumps(cand, sort_keys=True)
+        if s in seen or time.time() > t_end:
+            return
+        try:
+            ms = _time_plan(binding, descs, n, pixels, k, cells, cand)
+        except binding.LdpError:
+            return
+        seen[s] = ms
+        if verbose:
+            print("  %.4f ms %s" % (ms, s), flush=True)
+        if ms < best_ms:
+            best, best_ms = cand, ms
+
+    for _ in range(2):  # two sweeps of coordinate descent
+        for th in THREADS:
+            attempt(dict(best, block_threads=th))
+        for ci in range(len(best["classes"])):
+            cpis = sorted({1, 2, 4, cells[0]} & set(range(1, cells[0] + 1)))
+            for cpi in cpis:
+                cls = [dict(c) for c in best["classes"]]
+                cls[ci]["cell_rows_per_item"] = cpi
+                attempt(dict(best, classes=cls))
+            for rpt in ROWS_PER_TASK:
+                cls = [dict(c) for c in best["classes"]]
+                cls[ci]["rows_per_task"] = rpt
+                attempt(dict(best, classes=cls))
+    return best, best_ms
+
+
+def save(Hs, Ws, k, cells, tune, ms, path=CACHE, note=""):
+    cache = load_cache(path)
+    cache[key(Hs, Ws, k, cells)] = {"tune": tune, "ms": round(ms, 4), "note": note}
+    tmp = path + ".tmp%d" % os.getpid()
+    with open(tmp, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)

@@ -25,8 +25,8 @@ EXPORTED = [
     "ldp_status_string", "ldp_version", "ldp_codes", "ldp_histograms", "ldp_extract",
     "ldp_batch_plan_create", "ldp_batch_plan_set", "ldp_batch_run", "ldp_batch_run_per_image",
     "ldp_batch_plan_info", "ldp_batch_plan_destroy",
-    "ldp_server_create", "ldp_server_submit", "ldp_server_poll", "ldp_server_stats",
-    "ldp_server_destroy",
+    "ldp_now", "ldp_server_create", "ldp_server_submit", "ldp_server_poll",
+    "ldp_server_stats_get", "ldp_server_destroy",
 ]
 
 
@@ -41,9 +41,56 @@ class ImageDesc(ctypes.Structure):
                 ("stride", ctypes.c_int64), ("H", ctypes.c_int32), ("W", ctypes.c_int32)]
 
 
+MAX_SIZE_CLASSES = 4
+
+
+class SizeClass(ctypes.Structure):
+    _fields_ = [("max_pixels", ctypes.c_int64), ("cell_rows_per_item", ctypes.c_int32),
+                ("rows_per_task", ctypes.c_int32)]
+
+
 class Tune(ctypes.Structure):
-    _fields_ = [("cell_rows_per_item", ctypes.c_int32), ("block_threads", ctypes.c_int32),
-                ("grid_blocks", ctypes.c_int32), ("rows_per_task", ctypes.c_int32)]
+    _fields_ = [("block_threads", ctypes.c_int32), ("grid_blocks", ctypes.c_int32),
+                ("n_classes", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("classes", SizeClass * MAX_SIZE_CLASSES)]
+
+
+def make_tune(tune):
+    """ldp_tune from a dict {block_threads, grid_blocks, classes: [{max_pixels,
+    cell_rows_per_item, rows_per_task}, ...]} (missing fields take defaults)."""
+    t = Tune()
+    t.block_threads = int(tune.get("block_threads", 0))
+    t.grid_blocks = int(tune.get("grid_blocks", 0))
+    classes = tune.get("classes", [])
+    if len(classes) > MAX_SIZE_CLASSES:
+        raise ValueError("at most %d size classes" % MAX_SIZE_CLASSES)
+    t.n_classes = len(classes)
+    for i, c in enumerate(classes):
+        t.classes[i].max_pixels = int(c.get("max_pixels", 2 ** 62))
+        t.classes[i].cell_rows_per_item = int(c.get("cell_rows_per_item", 0))
+        t.classes[i].rows_per_task = int(c.get("rows_per_task", 0))
+    return t
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("pool_bytes", ctypes.c_int64), ("max_inflight", ctypes.c_int32),
+                ("max_batch", ctypes.c_int32), ("depth", ctypes.c_int32), ("k", ctypes.c_int32),
+                ("cells_y", ctypes.c_int32), ("cells_x", ctypes.c_int32),
+                ("dry_run", ctypes.c_int32), ("dry_run_us", ctypes.c_int32)]
+
+
+class Completion(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_done", ctypes.c_double), ("status", ctypes.c_int32),
+                ("batch_size", ctypes.c_int32)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("rejected", ctypes.c_int64), ("launches", ctypes.c_int64),
+                ("peak_pool_bytes", ctypes.c_int64), ("peak_inflight", ctypes.c_int32),
+                ("peak_batches", ctypes.c_int32), ("max_batch_seen", ctypes.c_int32),
+                ("waiting", ctypes.c_int32)]
 
 
 _lib = None
@@ -72,6 +119,13 @@ def load():
         "ldp_batch_run_per_image": (ctypes.c_int, [p, p]),
         "ldp_batch_plan_info": (ctypes.c_int, [p, ctypes.POINTER(i64), ctypes.POINTER(i32)]),
         "ldp_batch_plan_destroy": (ctypes.c_int, [p]),
+        "ldp_now": (ctypes.c_double, []),
+        "ldp_server_create": (ctypes.c_int, [ctypes.POINTER(p), ctypes.POINTER(ServerConfig)]),
+        "ldp_server_submit": (ctypes.c_int, [p, p, i32, i32, i64, p, p, ctypes.POINTER(i64)]),
+        "ldp_server_poll": (ctypes.c_int, [p, ctypes.POINTER(Completion), i32,
+                                           ctypes.POINTER(i32), i32]),
+        "ldp_server_stats_get": (ctypes.c_int, [p, ctypes.POINTER(ServerStats)]),
+        "ldp_server_destroy": (ctypes.c_int, [p]),
     }
     for name, (res, args) in sig.items():
         if not hasattr(lib, name):
@@ -158,10 +212,7 @@ class BatchPlan:
     def __init__(self, max_images, max_pixels, k, cells_y, cells_x, tune=None):
         self._lib = load()
         self._plan = ctypes.c_void_p()
-        t = None
-        if tune is not None:
-            t = Tune(*[int(tune.get(f, 0)) for f in ("cell_rows_per_item", "block_threads",
-                                                       "grid_blocks", "rows_per_task")])
+        t = make_tune(tune) if tune is not None else None
         _check(self._lib.ldp_batch_plan_create(ctypes.byref(self._plan), max_images, max_pixels,
                                                k, cells_y, cells_x,
                                                ctypes.byref(t) if t is not None else None),
@@ -211,5 +262,76 @@ class BatchPlan:
             pass
 
 
-def pointer_array(values):
-    return np.asarray(values, dtype=np.uint64)
+def now():
+    """The server clock (seconds, monotonic)."""
+    return load().ldp_now()
+
+
+class Server:
+    """Continuous-batching request server (ldp_server_*).
+
+    submit() takes HOST numpy buffers (page-locked ones, e.g. views of
+    torch.empty(..., pin_memory=True), give asynchronous copies); they are
+    kept alive here until the request completes.
+    """
+
+    def __init__(self, pool_bytes, max_inflight, max_batch, depth, k, cells_y, cells_x,
+                 dry_run=False, dry_run_us=0):
+        self._lib = load()
+        self._srv = ctypes.c_void_p()
+        cfg = ServerConfig(int(pool_bytes), int(max_inflight), int(max_batch), int(depth), int(k),
+                           int(cells_y), int(cells_x), 1 if dry_run else 0, int(dry_run_us))
+        _check(self._lib.ldp_server_create(ctypes.byref(self._srv), ctypes.byref(cfg)),
+               "ldp_server_create")
+        self.cells = (cells_y, cells_x)
+        self._live = {}
+
+    def submit(self, img, hist_out, codes_out=None):
+        a = img
+        if a.ndim != 2 or a.dtype != np.uint8 or a.strides[1] != 1:
+            raise ValueError("image must be a 2-D uint8 array with contiguous columns")
+        if hist_out.dtype not in (np.uint32, np.int32) or not hist_out.flags["C_CONTIGUOUS"]:
+            raise ValueError("hist_out must be a contiguous 32-bit array")
+        if hist_out.size != self.cells[0] * self.cells[1] * 256:
+            raise ValueError("hist_out has the wrong size")
+        H, W = a.shape
+        if codes_out is not None and (codes_out.dtype != np.uint8 or codes_out.size != (H - 2) * (W - 2)
+                                      or not codes_out.flags["C_CONTIGUOUS"]):
+            raise ValueError("codes_out must be a contiguous uint8 array of (H-2)*(W-2)")
+        rid = ctypes.c_int64()
+        _check(self._lib.ldp_server_submit(self._srv, a.ctypes.data, H, W, a.strides[0],
+                                           codes_out.ctypes.data if codes_out is not None else None,
+                                           hist_out.ctypes.data, ctypes.byref(rid)),
+               "ldp_server_submit")
+        self._live[rid.value] = (img, hist_out, codes_out)
+        return rid.value
+
+    def poll(self, max_n=4096, wait_us=0):
+        buf = (Completion * max_n)()
+        n = ctypes.c_int32()
+        _check(self._lib.ldp_server_poll(self._srv, buf, max_n, ctypes.byref(n), int(wait_us)),
+               "ldp_server_poll")
+        out = []
+        for i in range(n.value):
+            c = buf[i]
+            self._live.pop(c.id, None)
+            out.append(dict(id=c.id, t_submit=c.t_submit, t_admit=c.t_admit, t_done=c.t_done,
+                            status=c.status, batch_size=c.batch_size))
+        return out
+
+    def stats(self):
+        st = ServerStats()
+        _check(self._lib.ldp_server_stats_get(self._srv, ctypes.byref(st)), "ldp_server_stats_get")
+        return {f: getattr(st, f) for f, _ in ServerStats._fields_}
+
+    def close(self):
+        if self._srv:
+            self._lib.ldp_server_destroy(self._srv)
+            self._srv = ctypes.c_void_p()
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -8,6 +8,8 @@
 // persistent kernel) is captured once in a HIP graph when the plan is made;
 // the kernels read the item count and tables from device memory, so loading
 // a new batch never re-captures the graph.
+#include <stdint.h>
+
 #include <algorithm>
 #include <new>
 #include <numeric>
@@ -21,6 +23,7 @@ namespace ldp {
 struct Item {
     int32_t img;        // index into the descriptor table
     int16_t cy0, cy1;   // cell rows [cy0, cy1)
+    int32_t min_rows;   // target code rows per lane task
 };
 
 __global__ void clear_counter_kernel(uint32_t *meta) { meta[1] = 0; }
@@ -33,7 +36,7 @@ template <int K>
 __global__ void __launch_bounds__(1024) LDP_BATCH_ATTR batch_kernel(const ldp_image_desc *__restrict__ descs,
                                                      const Item *__restrict__ items,
                                                      uint32_t *meta, int32_t cells_y,
-                                                     int32_t cells_x, int32_t min_task_rows)
+                                                     int32_t cells_x)
 {
     extern __shared__ uint32_t lds[];
     __shared__ uint32_t s_item;
@@ -53,12 +56,11 @@ __global__ void __launch_bounds__(1024) LDP_BATCH_ATTR batch_kernel(const ldp_im
         const int32_t r1 = cell_start(w.cy1, im.Hc, cells_y);
         // a null code pointer gives an empty store range: stores are dropped
         fused_item<K, true>(im, lds, cells_y, cells_x, w.cy0, w.cy1, r0, r1, d.hist, false,
-                            min_task_rows);
+                            w.min_rows);
     }
 }
 
-typedef void (*batch_fn)(const ldp_image_desc *, const Item *, uint32_t *, int32_t, int32_t,
-                         int32_t);
+typedef void (*batch_fn)(const ldp_image_desc *, const Item *, uint32_t *, int32_t, int32_t);
 
 static batch_fn batch_kernel_for(int k)
 {
@@ -80,7 +82,9 @@ static batch_fn batch_kernel_for(int k)
 struct ldp_batch_plan {
     int32_t k = 3, cells_y = 1, cells_x = 1, max_images = 0;
     int64_t max_pixels = 0, max_items = 0;
-    int32_t threads = 256, cpi = 1, min_task_rows = 8, grid = 0;
+    int32_t threads = 256, grid = 0;
+    int32_t n_classes = 1;
+    ldp_size_class classes[LDP_MAX_SIZE_CLASSES] = {{INT64_MAX, 1, 8}};
     size_t lds_bytes = 0;
     int device = 0;
     ldp_image_desc *d_descs = nullptr;
@@ -138,21 +142,43 @@ int ldp_batch_plan_create(ldp_batch_plan **out, int32_t max_images, int64_t max_
     if (tune) {
         if (tune->block_threads)
             p->threads = tune->block_threads;
-        if (tune->cell_rows_per_item)
-            p->cpi = tune->cell_rows_per_item;
-        if (tune->rows_per_task)
-            p->min_task_rows = tune->rows_per_task;
         if (tune->grid_blocks)
             p->grid = tune->grid_blocks;
+        if (tune->n_classes < 0 || tune->n_classes > LDP_MAX_SIZE_CLASSES) {
+            delete p;
+            return LDP_ERR_INVALID_ARG;
+        }
+        if (tune->n_classes > 0) {
+            p->n_classes = tune->n_classes;
+            for (int c = 0; c < p->n_classes; ++c) {
+                ldp_size_class sc = tune->classes[c];
+                if (sc.cell_rows_per_item == 0)
+                    sc.cell_rows_per_item = 1;
+                if (sc.rows_per_task == 0)
+                    sc.rows_per_task = 8;
+                p->classes[c] = sc;
+            }
+        }
     }
-    if ((p->threads != 256 && p->threads != 512 && p->threads != 1024) || p->cpi < 1 ||
-        p->min_task_rows < 1 || p->grid < 0) {
+    if ((p->threads != 256 && p->threads != 512 && p->threads != 1024) || p->grid < 0) {
         delete p;
         return LDP_ERR_INVALID_ARG;
     }
-    p->cpi = std::min(p->cpi, cells_y);
-    p->max_items = (int64_t)max_images * ((cells_y + p->cpi - 1) / p->cpi);
-    p->lds_bytes = (size_t)(p->cpi * cells_x + 1) * 256 * sizeof(uint32_t);
+    int32_t max_cpi = 1, min_cpi = cells_y;
+    for (int c = 0; c < p->n_classes; ++c) {
+        ldp_size_class &sc = p->classes[c];
+        if (sc.cell_rows_per_item < 1 || sc.rows_per_task < 1 || sc.max_pixels < 1) {
+            delete p;
+            return LDP_ERR_INVALID_ARG;
+        }
+        sc.cell_rows_per_item = std::min(sc.cell_rows_per_item, cells_y);
+        max_cpi = std::max(max_cpi, sc.cell_rows_per_item);
+        min_cpi = std::min(min_cpi, sc.cell_rows_per_item);
+    }
+    p->classes[p->n_classes - 1].max_pixels = INT64_MAX;
+    p->max_items = (int64_t)max_images * ((cells_y + min_cpi - 1) / min_cpi);
+    // LDS: the largest item's cell rows plus the discard cell
+    p->lds_bytes = (size_t)(max_cpi * cells_x + 1) * 256 * sizeof(uint32_t);
     if (p->lds_bytes > 64 * 1024) {
         delete p;
         return LDP_ERR_UNSUPPORTED;
@@ -194,7 +220,7 @@ int ldp_batch_plan_create(ldp_batch_plan **out, int32_t max_images, int64_t max_
     hipLaunchKernelGGL(ldp::clear_counter_kernel, dim3(1), dim3(1), 0, p->cap_stream, p->d_meta);
     hipLaunchKernelGGL(fn, dim3(p->grid), dim3(p->threads), p->lds_bytes, p->cap_stream,
                        (const ldp_image_desc *)p->d_descs, (const ldp::Item *)p->d_items,
-                       p->d_meta, cells_y, cells_x, p->min_task_rows);
+                       p->d_meta, cells_y, cells_x);
     hipError_t ce = hipStreamEndCapture(p->cap_stream, &p->graph);
     if (ce != hipSuccess || hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) !=
                                 hipSuccess)
@@ -226,19 +252,26 @@ int ldp_batch_plan_set(ldp_batch_plan *p, const ldp_image_desc *descs, int32_t n
     if (hipEventSynchronize(p->uploaded) != hipSuccess)
         return LDP_ERR_HIP;
     p->descs.assign(descs, descs + n);
-    // work items: groups of cpi cell rows, largest first
+    // work items: per image, groups of its size class's cell rows; largest first
     std::vector<ldp::Item> items;
-    items.reserve((size_t)n * ((p->cells_y + p->cpi - 1) / p->cpi));
     std::vector<int64_t> size;
     for (int32_t j = 0; j < n; ++j) {
+        const int64_t px = (int64_t)descs[j].H * descs[j].W;
+        int c = 0;
+        while (c < p->n_classes - 1 && px > p->classes[c].max_pixels)
+            ++c;
+        const int32_t cpi = p->classes[c].cell_rows_per_item;
         const int32_t Hc = descs[j].H - 2;
-        for (int32_t cy = 0; cy < p->cells_y; cy += p->cpi) {
-            int32_t cy1 = std::min(cy + p->cpi, p->cells_y);
-            items.push_back({j, (int16_t)cy, (int16_t)cy1});
-            int64_t rows = ldp::cell_start(cy1, Hc, p->cells_y) - ldp::cell_start(cy, Hc, p->cells_y);
+        for (int32_t cy = 0; cy < p->cells_y; cy += cpi) {
+            const int32_t cy1 = std::min(cy + cpi, p->cells_y);
+            items.push_back({j, (int16_t)cy, (int16_t)cy1, p->classes[c].rows_per_task});
+            const int64_t rows =
+                ldp::cell_start(cy1, Hc, p->cells_y) - ldp::cell_start(cy, Hc, p->cells_y);
             size.push_back(rows * (descs[j].W - 2));
         }
     }
+    if ((int64_t)items.size() > p->max_items)
+        return LDP_ERR_NO_MEMORY;
     std::vector<int64_t> order(items.size());
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(),

@@ -1,0 +1,408 @@
+// ldp_serve.hip -- continuous-batching request server (host code).
+//
+// Requests wait in arrival order until the device pool has room for their
+// image, codes and histograms and a request slot is free.  A dispatcher
+// thread admits as many waiting requests as fit (up to max_batch), copies
+// their images to the pool and launches them as one persistent batch (a batch
+// plan: device descriptor and work tables, device work queue, captured graph)
+// on a free stream, then copies the results back.  Up to `depth` batches are
+// in flight, so requests that arrive while earlier batches run are admitted as
+// soon as memory and slots free up and run concurrently with them.  When a
+// batch's completion event has fired its requests are reported done and their
+// memory and slots are released.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "ldp_host.hpp"
+
+namespace {
+
+double now_s()
+{
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+int64_t round256(int64_t n) { return (n + 255) & ~int64_t(255); }
+
+// First-fit allocator over [0, size) with coalescing of neighbours.
+class Pool {
+public:
+    explicit Pool(int64_t size) : size_(size) { free_[0] = size; }
+    int64_t alloc(int64_t n)
+    {
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= n) {
+                const int64_t off = it->first, rest = it->second - n;
+                free_.erase(it);
+                if (rest)
+                    free_[off + n] = rest;
+                used_ += n;
+                return off;
+            }
+        }
+        return -1;
+    }
+    void release(int64_t off, int64_t n)
+    {
+        used_ -= n;
+        auto it = free_.emplace(off, n).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    int64_t used() const { return used_; }
+    int64_t size() const { return size_; }
+
+private:
+    std::map<int64_t, int64_t> free_;
+    int64_t size_, used_ = 0;
+};
+
+struct Req {
+    int64_t id;
+    const uint8_t *img;
+    int32_t H, W;
+    int64_t stride;
+    uint8_t *codes;
+    uint32_t *hist;
+    double t_submit, t_admit = 0;
+    int64_t off = -1, bytes = 0, img_bytes = 0, code_bytes = 0;
+};
+
+struct Batch {
+    std::vector<Req *> reqs;
+    int slot = -1;
+    double t_launch = 0;
+    int status = LDP_OK;
+};
+
+}  // namespace
+
+struct ldp_server {
+    ldp_server_config cfg{};
+    int64_t hist_bytes = 0;
+    uint8_t *d_pool = nullptr;
+    Pool *pool = nullptr;
+    std::vector<hipStream_t> streams;
+    std::vector<hipEvent_t> events;
+    std::vector<ldp_batch_plan *> plans;
+    std::vector<char> slot_busy;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Req *> pending;
+    std::vector<Batch> inflight;
+    std::deque<ldp_completion> done;
+    int inflight_reqs = 0;
+    bool stop = false;
+    int64_t next_id = 0;
+    ldp_server_stats st{};
+    int device = 0;
+    std::thread th;
+};
+
+namespace {
+
+// Device work of one batch on its stream; returns a status.
+int launch_batch(ldp_server *s, Batch &b)
+{
+    if (s->cfg.dry_run)
+        return LDP_OK;
+    hipStream_t st = s->streams[b.slot];
+    std::vector<ldp_image_desc> descs;
+    descs.reserve(b.reqs.size());
+    for (Req *r : b.reqs) {
+        uint8_t *dimg = s->d_pool + r->off;
+        uint8_t *dcodes = r->codes ? dimg + r->img_bytes : nullptr;
+        uint32_t *dhist = reinterpret_cast<uint32_t *>(dimg + r->img_bytes + r->code_bytes);
+        if (hipMemcpy2DAsync(dimg, r->W, r->img, r->stride, r->W, r->H, hipMemcpyHostToDevice,
+                             st) != hipSuccess)
+            return LDP_ERR_HIP;
+        descs.push_back({dimg, dcodes, dhist, (int64_t)r->W, r->H, r->W});
+    }
+    int rc = ldp_batch_plan_set(s->plans[b.slot], descs.data(), (int32_t)descs.size(),
+                                (ldp_stream_t)st);
+    if (rc == LDP_OK)
+        rc = ldp_batch_run(s->plans[b.slot], (ldp_stream_t)st);
+    if (rc != LDP_OK)
+        return rc;
+    for (size_t i = 0; i < b.reqs.size(); ++i) {
+        Req *r = b.reqs[i];
+        if (hipMemcpyAsync(r->hist, descs[i].hist, s->hist_bytes, hipMemcpyDeviceToHost, st) !=
+            hipSuccess)
+            return LDP_ERR_HIP;
+        if (r->codes && hipMemcpyAsync(r->codes, descs[i].codes, (size_t)(r->H - 2) * (r->W - 2),
+                                       hipMemcpyDeviceToHost, st) != hipSuccess)
+            return LDP_ERR_HIP;
+    }
+    return hipEventRecord(s->events[b.slot], st) == hipSuccess ? LDP_OK : LDP_ERR_HIP;
+}
+
+bool batch_finished(ldp_server *s, Batch &b, double t)
+{
+    if (s->cfg.dry_run)
+        return t >= b.t_launch + s->cfg.dry_run_us * 1e-6;
+    hipError_t e = hipEventQuery(s->events[b.slot]);
+    if (e == hipErrorNotReady)
+        return false;
+    if (e != hipSuccess)
+        b.status = LDP_ERR_HIP;
+    return true;
+}
+
+void dispatcher(ldp_server *s)
+{
+    if (!s->cfg.dry_run)
+        (void)hipSetDevice(s->device);
+    std::unique_lock<std::mutex> lk(s->mu);
+    for (;;) {
+        bool progressed = false;
+        // retire finished batches: report, then free memory and slots
+        const double t = now_s();
+        for (size_t i = 0; i < s->inflight.size();) {
+            Batch &b = s->inflight[i];
+            if (!batch_finished(s, b, t)) {
+                ++i;
+                continue;
+            }
+            for (Req *r : b.reqs) {
+                s->pool->release(r->off, r->bytes);
+                s->done.push_back({r->id, r->t_submit, r->t_admit, t, b.status,
+                                   (int32_t)b.reqs.size()});
+                delete r;
+            }
+            s->inflight_reqs -= (int)b.reqs.size();
+            s->st.completed += (int64_t)b.reqs.size();
+            s->slot_busy[b.slot] = 0;
+            s->inflight.erase(s->inflight.begin() + (long)i);
+            progressed = true;
+        }
+        if (progressed)
+            s->cv_done.notify_all();
+        // admit waiting requests in arrival order into a free launch slot
+        int slot = -1;
+        for (int i = 0; i < (int)s->slot_busy.size(); ++i)
+            if (!s->slot_busy[i]) {
+                slot = i;
+                break;
+            }
+        if (slot >= 0 && !s->pending.empty()) {
+            Batch b;
+            b.slot = slot;
+            while (!s->pending.empty() && (int)b.reqs.size() < s->cfg.max_batch &&
+                   s->inflight_reqs + (int)b.reqs.size() < s->cfg.max_inflight) {
+                Req *r = s->pending.front();
+                const int64_t off = s->pool->alloc(r->bytes);
+                if (off < 0)
+                    break;  // head of line waits for memory
+                r->off = off;
+                r->t_admit = now_s();
+                s->pending.pop_front();
+                b.reqs.push_back(r);
+            }
+            if (!b.reqs.empty()) {
+                s->slot_busy[slot] = 1;
+                s->inflight_reqs += (int)b.reqs.size();
+                s->st.peak_inflight = std::max(s->st.peak_inflight, s->inflight_reqs);
+                s->st.peak_pool_bytes = std::max(s->st.peak_pool_bytes, s->pool->used());
+                s->st.max_batch_seen = std::max(s->st.max_batch_seen, (int32_t)b.reqs.size());
+                s->st.launches += 1;
+                // device work without the lock: submit() keeps running
+                lk.unlock();
+                b.status = launch_batch(s, b);
+                b.t_launch = now_s();
+                lk.lock();
+                s->inflight.push_back(std::move(b));
+                s->st.peak_batches = std::max(s->st.peak_batches, (int32_t)s->inflight.size());
+                progressed = true;
+            }
+        }
+        s->st.waiting = (int32_t)s->pending.size();
+        if (s->stop && s->pending.empty() && s->inflight.empty())
+            break;
+        if (!progressed) {
+            if (s->inflight.empty())
+                s->cv_work.wait_for(lk, std::chrono::milliseconds(2));
+            else {
+                lk.unlock();
+                std::this_thread::sleep_for(std::chrono::microseconds(20));
+                lk.lock();
+            }
+        }
+    }
+}
+
+void release_server(ldp_server *s)
+{
+    for (ldp_batch_plan *p : s->plans)
+        if (p)
+            ldp_batch_plan_destroy(p);
+    for (hipEvent_t e : s->events)
+        if (e)
+            (void)hipEventDestroy(e);
+    for (hipStream_t st : s->streams)
+        if (st)
+            (void)hipStreamDestroy(st);
+    if (s->d_pool)
+        (void)hipFree(s->d_pool);
+    delete s->pool;
+    for (Req *r : s->pending)
+        delete r;
+    delete s;
+}
+
+}  // namespace
+
+extern "C" {
+
+double ldp_now(void) { return now_s(); }
+
+int ldp_server_create(ldp_server **out, const ldp_server_config *cfg)
+{
+    if (!out || !cfg)
+        return LDP_ERR_INVALID_ARG;
+    *out = nullptr;
+    const ldp_server_config c = *cfg;
+    if (c.pool_bytes < 4096 || c.max_inflight < 1 || c.max_batch < 1 || c.depth < 1 ||
+        c.depth > 8 || c.k < 1 || c.k > 8 || c.cells_y < 1 || c.cells_x < 1 ||
+        c.cells_x > ldp::kMaxFusedCellsX || c.dry_run_us < 0)
+        return LDP_ERR_INVALID_ARG;
+    ldp_server *s = new (std::nothrow) ldp_server();
+    if (!s)
+        return LDP_ERR_NO_MEMORY;
+    s->cfg = c;
+    s->hist_bytes = (int64_t)c.cells_y * c.cells_x * 256 * 4;
+    s->pool = new Pool(c.pool_bytes);
+    s->slot_busy.assign(c.depth, 0);
+    if (!c.dry_run) {
+        if (hipGetDevice(&s->device) != hipSuccess) {
+            release_server(s);
+            return LDP_ERR_HIP;
+        }
+        if (hipMalloc(&s->d_pool, (size_t)c.pool_bytes) != hipSuccess) {
+            release_server(s);
+            return LDP_ERR_NO_MEMORY;
+        }
+        for (int i = 0; i < c.depth; ++i) {
+            hipStream_t st = nullptr;
+            hipEvent_t ev = nullptr;
+            ldp_batch_plan *p = nullptr;
+            if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess ||
+                hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+                if (st)
+                    (void)hipStreamDestroy(st);
+                release_server(s);
+                return LDP_ERR_HIP;
+            }
+            s->streams.push_back(st);
+            s->events.push_back(ev);
+            int rc = ldp_batch_plan_create(&p, c.max_batch, c.pool_bytes, c.k, c.cells_y,
+                                           c.cells_x, nullptr);
+            if (rc != LDP_OK) {
+                release_server(s);
+                return rc;
+            }
+            s->plans.push_back(p);
+        }
+    }
+    s->th = std::thread(dispatcher, s);
+    *out = s;
+    return LDP_OK;
+}
+
+int ldp_server_submit(ldp_server *s, const uint8_t *img, int32_t H, int32_t W, int64_t stride,
+                      uint8_t *codes, uint32_t *hist, int64_t *id)
+{
+    if (!s || !img || !hist || !id || H < 3 || W < 3 || H > LDP_MAX_SIDE || W > LDP_MAX_SIDE ||
+        stride < W || H - 2 < s->cfg.cells_y || W - 2 < s->cfg.cells_x)
+        return LDP_ERR_INVALID_ARG;
+    if ((int64_t)(H - 1) * W + W + 8 > ldp::kMaxExtent)
+        return LDP_ERR_UNSUPPORTED;
+    Req *r = new (std::nothrow) Req();
+    if (!r)
+        return LDP_ERR_NO_MEMORY;
+    r->img = img;
+    r->H = H;
+    r->W = W;
+    r->stride = stride;
+    r->codes = codes;
+    r->hist = hist;
+    r->img_bytes = round256((int64_t)H * W);
+    r->code_bytes = codes ? round256((int64_t)(H - 2) * (W - 2)) : 0;
+    r->bytes = r->img_bytes + r->code_bytes + round256(s->hist_bytes);
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (r->bytes > s->pool->size()) {
+        s->st.rejected += 1;
+        delete r;
+        return LDP_ERR_NO_MEMORY;
+    }
+    r->id = s->next_id++;
+    r->t_submit = now_s();
+    *id = r->id;
+    s->pending.push_back(r);
+    s->st.submitted += 1;
+    s->cv_work.notify_one();
+    return LDP_OK;
+}
+
+int ldp_server_poll(ldp_server *s, ldp_completion *out, int32_t max, int32_t *n, int32_t wait_us)
+{
+    if (!s || !n || max < 0 || (max > 0 && !out))
+        return LDP_ERR_INVALID_ARG;
+    std::unique_lock<std::mutex> lk(s->mu);
+    if (s->done.empty() && wait_us > 0)
+        s->cv_done.wait_for(lk, std::chrono::microseconds(wait_us),
+                            [&] { return !s->done.empty(); });
+    int32_t k = 0;
+    while (k < max && !s->done.empty()) {
+        out[k++] = s->done.front();
+        s->done.pop_front();
+    }
+    *n = k;
+    return LDP_OK;
+}
+
+int ldp_server_stats_get(ldp_server *s, ldp_server_stats *stats)
+{
+    if (!s || !stats)
+        return LDP_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(s->mu);
+    *stats = s->st;
+    stats->waiting = (int32_t)s->pending.size();
+    return LDP_OK;
+}
+
+int ldp_server_destroy(ldp_server *s)
+{
+    if (!s)
+        return LDP_ERR_INVALID_ARG;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+        s->cv_work.notify_one();
+    }
+    if (s->th.joinable())
+        s->th.join();
+    release_server(s);
+    return LDP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,78 @@
+"""The C ABI library: loads, exports every symbol include/ldp.h declares,
+and rejects invalid arguments on the host before touching a GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1810_11518_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "ldp.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(ldp_\w+)\s*\(", text)
+    return sorted(set(n for n in names if not n.endswith("_t")))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(binding.LIB_PATH):
+        from paper_1810_11518_amd import build
+        build.build()
+    return binding.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared_functions()
+    assert len(names) >= 15
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(names) <= set(binding.EXPORTED) | {"ldp_stream_t"}
+
+
+def test_status_strings_and_version(lib):
+    assert lib.ldp_version() == 1
+    assert lib.ldp_status_string(0) == b"ok"
+    assert b"invalid" in lib.ldp_status_string(-1)
+
+
+def test_invalid_arguments_return_before_any_launch(lib):
+    p = ctypes.c_void_p(0x1000)   # never dereferenced: validation fails first
+    E = binding.LDP_ERR_INVALID_ARG
+    assert lib.ldp_codes(None, 10, 10, 10, 3, p, None) == E
+    assert lib.ldp_codes(p, 2, 10, 10, 3, p, None) == E
+    assert lib.ldp_codes(p, 10, 2, 10, 3, p, None) == E
+    assert lib.ldp_codes(p, 10, 10, 9, 3, p, None) == E
+    assert lib.ldp_codes(p, 10, 10, 10, 0, p, None) == E
+    assert lib.ldp_codes(p, 10, 10, 10, 9, p, None) == E
+    assert lib.ldp_codes(p, 10, 70000, 70000, 3, p, None) == E
+    assert lib.ldp_histograms(p, 10, 10, 9, 1, p, None) == E
+    assert lib.ldp_histograms(p, 10, 10, 1, 0, p, None) == E
+    assert lib.ldp_extract(p, 10, 10, 10, 3, 1, 1, None, None, None) == E
+    assert lib.ldp_extract(p, 10, 10, 10, 3, 0, 1, p, p, None) == E
+    assert lib.ldp_codes(p, 40000, 60000, 60000, 3, p, None) == binding.LDP_ERR_UNSUPPORTED
+    plan = ctypes.c_void_p()
+    assert lib.ldp_batch_plan_create(ctypes.byref(plan), 0, 100, 3, 7, 6, None) == E
+    assert lib.ldp_batch_plan_create(ctypes.byref(plan), 10, 100, 9, 7, 6, None) == E
+    assert lib.ldp_batch_plan_create(ctypes.byref(plan), 10, 100, 3, 7, 200, None) == E
+    t = binding.make_tune(dict(block_threads=300))
+    assert lib.ldp_batch_plan_create(ctypes.byref(plan), 10, 100, 3, 7, 6, ctypes.byref(t)) == E
+    assert lib.ldp_batch_run(None, None) == E
+    srv = ctypes.c_void_p()
+    bad = binding.ServerConfig(0, 1, 1, 1, 3, 7, 6, 1, 0)
+    assert lib.ldp_server_create(ctypes.byref(srv), ctypes.byref(bad)) == E
+    bad = binding.ServerConfig(1 << 20, 1, 1, 9, 3, 7, 6, 1, 0)
+    assert lib.ldp_server_create(ctypes.byref(srv), ctypes.byref(bad)) == E
+
+
+def test_tune_struct_layout():
+    t = binding.make_tune(dict(block_threads=512, classes=[dict(max_pixels=10, cell_rows_per_item=2,
+                                                                 rows_per_task=4), {}]))
+    assert ctypes.sizeof(binding.Tune) == 16 + 4 * 16
+    assert t.n_classes == 2 and t.classes[0].max_pixels == 10 and t.classes[1].cell_rows_per_item == 0
+    assert ctypes.sizeof(binding.ImageDesc) == 40

@@ -79,9 +79,13 @@ def test_uneven_batch_matches_oracle(lib, k):
         b.check(j, k, (7, 6))
 
 
-@pytest.mark.parametrize("tune", [dict(block_threads=256), dict(block_threads=1024, rows_per_task=16),
-                                  dict(cell_rows_per_item=3, block_threads=512),
-                                  dict(cell_rows_per_item=7, grid_blocks=5)])
+@pytest.mark.parametrize("tune", [
+    dict(block_threads=256), dict(block_threads=1024, classes=[dict(rows_per_task=16)]),
+    dict(block_threads=512, classes=[dict(cell_rows_per_item=3)]),
+    dict(grid_blocks=5, classes=[dict(cell_rows_per_item=7)]),
+    dict(block_threads=512, classes=[dict(max_pixels=20000, cell_rows_per_item=7, rows_per_task=2),
+                                     dict(max_pixels=60000, cell_rows_per_item=2, rows_per_task=4),
+                                     dict(cell_rows_per_item=1, rows_per_task=32)])])
 def test_tunings_give_identical_results(lib, tune):
     r = np.random.default_rng(7)
     n = 24

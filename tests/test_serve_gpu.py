@@ -1,0 +1,125 @@
+"""The request server on the GPU: every result equals the oracle, and is the
+same when the request runs alone as when it runs in a mix of concurrent,
+overlapping batches."""
+import time
+
+import numpy as np
+import pytest
+
+from conftest import gpu_available
+from oracle import native as oracle_c
+from paper_1810_11518_amd import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not gpu_available():
+        pytest.skip("no GPU")
+    from paper_1810_11518_amd import binding
+    binding.load()
+    torch.zeros(1, device="cuda")
+    return binding
+
+
+def _pinned(shape, dtype):
+    t = torch.empty(int(np.prod(shape)) * np.dtype(dtype).itemsize, dtype=torch.uint8,
+                    pin_memory=True)
+    return t, t.numpy().view(dtype).reshape(shape)
+
+
+def _requests(n, seed):
+    r = np.random.default_rng(seed)
+    out = []
+    for j in range(n):
+        H, W = int(r.integers(12, 700)), int(r.integers(12, 900))
+        keep, img = _pinned((H, W), np.uint8)
+        img[:] = synth.image(synth.KIND_BLUR_RECTS, seed, j, H, W)
+        out.append((keep, img))
+    return out
+
+
+def _outputs(H, W):
+    kc, codes = _pinned(((H - 2) * (W - 2),), np.uint8)
+    kh, hist = _pinned((7 * 6 * 256,), np.uint32)
+    return (kc, kh), codes, hist
+
+
+def _drain(srv, n, timeout=60.0):
+    done = []
+    t0 = time.time()
+    while len(done) < n and time.time() - t0 < timeout:
+        done += srv.poll(wait_us=20000)
+    assert len(done) == n, "server did not finish"
+    return done
+
+
+def test_serving_alone_equals_mix_equals_oracle(lib):
+    reqs = _requests(40, 3)
+    # alone: one request in flight at a time
+    srv = lib.Server(1 << 28, 64, 16, 4, 3, 7, 6)
+    alone = []
+    for keep, img in reqs:
+        k, codes, hist = _outputs(*img.shape)
+        srv.submit(img, hist, codes)
+        _drain(srv, 1)
+        alone.append((codes.copy(), hist.copy()))
+    # mix: a burst plus staggered arrivals, up to 4 batches in flight
+    mix = []
+    keeps = []
+    for j, (keep, img) in enumerate(reqs):
+        k, codes, hist = _outputs(*img.shape)
+        keeps.append(k)
+        mix.append((codes, hist))
+        srv.submit(img, hist, codes)
+        if j % 10 == 9:
+            time.sleep(0.002)
+    done = _drain(srv, len(reqs))
+    st = srv.stats()
+    srv.close()
+    assert all(d["status"] == 0 for d in done)
+    for (keep, img), (ca, ha), (cm, hm) in zip(reqs, alone, mix):
+        want_c, want_h = oracle_c.ldp_extract(img, 3, 7, 6)
+        assert (ca.reshape(want_c.shape) == want_c).all() and (ha.reshape(want_h.shape) == want_h).all()
+        assert (cm == ca).all() and (hm == ha).all()
+    assert st["launches"] >= 40 + 3
+
+
+def test_batches_overlap_and_memory_limits_hold(lib):
+    reqs = _requests(64, 4)
+    pool = 6 << 20
+    srv = lib.Server(pool, 24, 8, 4, 3, 7, 6)
+    outs = []
+    for keep, img in reqs:
+        k, codes, hist = _outputs(*img.shape)
+        outs.append((k, codes, hist))
+        srv.submit(img, hist, codes)
+    done = _drain(srv, len(reqs))
+    st = srv.stats()
+    srv.close()
+    assert st["peak_pool_bytes"] <= pool and st["peak_inflight"] <= 24 and st["max_batch_seen"] <= 8
+    assert st["peak_batches"] >= 2
+    # some request was admitted while an earlier batch was still on the GPU
+    done.sort(key=lambda d: d["t_admit"])
+    assert any(b["t_admit"] < a["t_done"] and b["t_admit"] > a["t_admit"]
+               for a, b in zip(done, done[1:]))
+    for (keep, img), (k, codes, hist) in zip(reqs, outs):
+        want_c, want_h = oracle_c.ldp_extract(img, 3, 7, 6)
+        assert (codes.reshape(want_c.shape) == want_c).all()
+        assert (hist.reshape(want_h.shape) == want_h).all()
+
+
+def test_histograms_only_requests(lib):
+    reqs = _requests(10, 5)
+    srv = lib.Server(1 << 26, 16, 8, 2, 3, 7, 6)
+    hists = []
+    for keep, img in reqs:
+        k, codes, hist = _outputs(*img.shape)
+        hists.append((k, hist))
+        srv.submit(img, hist)
+    _drain(srv, len(reqs))
+    srv.close()
+    for (keep, img), (k, hist) in zip(reqs, hists):
+        assert (hist.reshape(7, 6, 256) == oracle_c.ldp_extract(img, 3, 7, 6)[1]).all()
