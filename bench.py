@@ -21,6 +21,21 @@ sys.path.insert(0, ROOT)
 
 METRIC = "LDP Mpixel/s + % HBM roofline (batched vs plain kernel); p50/p99 serve latency"
 HBM_PEAK_GBS = 8000.0
+# VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one wave64 VALU
+# instruction per SIMD every 4 cycles), in tera lane-instructions per second
+VALU_PEAK_T = 256 * 4 * 16 * 2.4e9 / 1e12
+
+
+def kernel_sources_hash():
+    import glob
+    import hashlib
+    src = sorted(glob.glob(os.path.join(ROOT, "paper_1810_11518_amd", "csrc", "*.hip")) +
+                 glob.glob(os.path.join(ROOT, "paper_1810_11518_amd", "csrc", "*.hpp")))
+    h = hashlib.sha256()
+    for f in src:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def parse():
@@ -83,6 +98,14 @@ def serve_bench(binding, synth, rates, seconds, k=3, cells=(7, 6), pool_images=2
         arr, _, _ = synth.serve_stream(rate, n)
         srv = binding.Server(4 << 30, max_inflight=1024, max_batch=256, depth=4, k=k,
                              cells_y=cells[0], cells_x=cells[1])
+        # warm-up: every launch slot runs a few batches before the timed stream
+        for w in range(64):
+            srv.submit(imgs[w % pool_images], outs[w % nout])
+            if w % 8 == 7:
+                time.sleep(0.001)
+        got = 0
+        while got < 64:
+            got += len(srv.poll(wait_us=5000))
         t0 = binding.now() + 0.02
         sched = t0 + arr
         lat = np.zeros(n)
@@ -114,7 +137,7 @@ def serve_bench(binding, synth, rates, seconds, k=3, cells=(7, 6), pool_images=2
                         "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
                         "mean_batch": round(float(sizes.mean()), 1),
                         "peak_batches_in_flight": st["peak_batches"],
-                        "launches": st["launches"]})
+                        "launches_incl_warmup": st["launches"]})
     return results
 
 
@@ -224,12 +247,16 @@ def main():
     mpix = pixels / (ms_step * 1e-3) / 1e6
     mpix_plain = pixels / (ms_plain * 1e-3) / 1e6 if ms_plain else None
 
-    traffic = None
+    # HBM bytes and VALU instructions per launch from the committed rocprofv3
+    # counters, valid only for the kernel sources they were taken with
+    traffic = valu = None
     if os.path.exists(args.traffic):
         with open(args.traffic) as f:
             tr = json.load(f).get(args.workload)
-        if tr and tr.get("k") == k:
+        if tr and tr.get("k") == k and tr.get("kernel_sources_sha256_16") == kernel_sources_hash():
             traffic = tr.get("bytes_per_launch")
+            valu = tr.get("valu_wave_instructions_per_launch")
+    alu_achieved = valu * 64 / (ms_event * 1e-3) / 1e12 if valu else None
 
     cpu = None
     if not args.no_cpu:
@@ -250,7 +277,7 @@ def main():
                          "single thread, %.1f s" % (ncpu, n, dt)}
 
     serve = None
-    if args.serve_rates:
+    if args.serve_rates and args.serve_rates.strip():
         rates = [int(x) for x in args.serve_rates.split(",") if x]
         serve = {"workload": "Poisson arrivals, single uint8 images, sides log-uniform in "
                              "[64,2048], k=3, 7x6 cells, histogram outputs; latency from "
@@ -277,9 +304,15 @@ def main():
                                                               cells[0], cells[1]),
                    "images": n, "pixels": pixels, "k": k, "cells": list(cells),
                    "work_items": items, "grid_blocks": grid, "tune": tune, "tune_source": tune_src},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "algorithmic_bytes_per_launch": abytes},
+        "roofline": {"bound": "alu", "unit": "T VALU lane-instr/s",
+                     "achieved": round(alu_achieved, 2) if alu_achieved else None,
+                     "peak": round(VALU_PEAK_T, 2),
+                     "frac": round(alu_achieved / VALU_PEAK_T, 4) if alu_achieved else None,
+                     "traffic": traffic,
+                     "hbm": {"achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": round(achieved / HBM_PEAK_GBS, 4),
+                             "algorithmic_bytes_per_launch": abytes},
+                     "kernel": "batch_kernel<%d>" % k},
         "plain": None if not ms_plain else {
             "value": round(mpix_plain, 1), "unit": "Mpixel/s", "ms_per_step": round(ms_plain, 3),
             "frac": round(abytes / (ms_plain * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),

@@ -133,8 +133,12 @@ int launch_batch(ldp_server *s, Batch &b)
         uint8_t *dimg = s->d_pool + r->off;
         uint8_t *dcodes = r->codes ? dimg + r->img_bytes : nullptr;
         uint32_t *dhist = reinterpret_cast<uint32_t *>(dimg + r->img_bytes + r->code_bytes);
-        if (hipMemcpy2DAsync(dimg, r->W, r->img, r->stride, r->W, r->H, hipMemcpyHostToDevice,
-                             st) != hipSuccess)
+        const hipError_t e =
+            r->stride == r->W
+                ? hipMemcpyAsync(dimg, r->img, (size_t)r->H * r->W, hipMemcpyHostToDevice, st)
+                : hipMemcpy2DAsync(dimg, r->W, r->img, r->stride, r->W, r->H,
+                                   hipMemcpyHostToDevice, st);
+        if (e != hipSuccess)
             return LDP_ERR_HIP;
         descs.push_back({dimg, dcodes, dhist, (int64_t)r->W, r->H, r->W});
     }
