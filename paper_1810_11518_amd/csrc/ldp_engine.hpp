@@ -49,10 +49,11 @@ __device__ __forceinline__ ImgView make_view(const uint8_t *img, int64_t stride,
 }
 
 // First code row (column) of cell `c` in a floor partition of n rows into
-// `cells` cells: the smallest r with r*cells/n == c.
+// `cells` cells: the smallest r with r*cells/n == c.  c <= cells <= n <= 65534,
+// so c*n + cells - 1 < 2^32 and unsigned 32-bit arithmetic is exact.
 __host__ __device__ __forceinline__ int32_t cell_start(int32_t c, int32_t n, int32_t cells)
 {
-    return (int32_t)(((int64_t)c * n + cells - 1) / cells);
+    return (int32_t)(((uint32_t)c * (uint32_t)n + (uint32_t)cells - 1u) / (uint32_t)cells);
 }
 
 // LDS histogram window: cell rows [cy0, cy0 + ncy) x cells_x cells of 256
@@ -149,7 +150,7 @@ __device__ __forceinline__ void run_task(const ImgView &im, const HistWin &hw, i
         const uint32_t rowb = (uint32_t)((cy - hw.cy0) * hw.cells_x) * 1024u;
 #pragma unroll
         for (int p = 0; p < 8; ++p) {
-            uint32_t cx = (uint32_t)(((int64_t)(j0 + p) * hw.cells_x) / im.Wc);
+            const uint32_t cx = ((uint32_t)(j0 + p) * (uint32_t)hw.cells_x) / (uint32_t)im.Wc;
             w.cb[p] = p < skip ? hw.discard() : rowb + cx * 1024u;
         }
         w.uniform_cell = skip == 0 && w.cb[0] == w.cb[7];
@@ -170,6 +171,17 @@ __device__ __forceinline__ void run_task(const ImgView &im, const HistWin &hw, i
     // the three rows rotate through A, B, C (and the vertical pair sums
     // through VAB, VBC, VCA) so no registers are copied between rows
     int32_t n = r1 - r0;
+#ifdef LDP_ROLLED_ROWS
+    for (; n > 0; --n) {
+        step<K, HIST, CODES>(im, hw, w, raw, A, B, C, VAB, VBC);
+        A = B;
+        B = C;
+#pragma unroll
+        for (int a = 0; a < 6; ++a)
+            VAB[a] = VBC[a];
+    }
+    (void)VCA;
+#else
     for (; n >= 3; n -= 3) {
         step<K, HIST, CODES>(im, hw, w, raw, A, B, C, VAB, VBC);
         step<K, HIST, CODES>(im, hw, w, raw, B, C, A, VBC, VCA);
@@ -179,6 +191,7 @@ __device__ __forceinline__ void run_task(const ImgView &im, const HistWin &hw, i
         step<K, HIST, CODES>(im, hw, w, raw, A, B, C, VAB, VBC);
     if (n >= 2)
         step<K, HIST, CODES>(im, hw, w, raw, B, C, A, VBC, VCA);
+#endif
 }
 
 // Code rows [r0, r1) of a code map narrower than 8 columns: one lane, the
@@ -249,8 +262,8 @@ __device__ __forceinline__ void run_rows(const ImgView &im, const HistWin &hw, i
     if (im.Wc < 8) {
         const int32_t nsub = min(nthreads, nr);
         if (tid < nsub) {
-            const int32_t a0 = r0 + (int32_t)((int64_t)nr * tid / nsub);
-            const int32_t a1 = r0 + (int32_t)((int64_t)nr * (tid + 1) / nsub);
+            const int32_t a0 = r0 + (int32_t)(((uint32_t)nr * tid) / (uint32_t)nsub);
+            const int32_t a1 = r0 + (int32_t)(((uint32_t)nr * (tid + 1)) / (uint32_t)nsub);
             if (a1 > a0)
                 run_task_narrow<K, HIST, CODES>(im, hw, a0, a1, cy);
         }
@@ -261,13 +274,14 @@ __device__ __forceinline__ void run_rows(const ImgView &im, const HistWin &hw, i
     // shorter than min_task_rows code rows
     const int32_t nsub =
         max(1, min(nthreads / ngroups, (nr + min_task_rows - 1) / min_task_rows));
-    const int32_t ntasks = ngroups * nsub;
-    for (int32_t task = tid; task < ntasks; task += nthreads) {
-        const int32_t g = task % ngroups, sb = task / ngroups;
-        const int32_t a0 = r0 + (int32_t)((int64_t)nr * sb / nsub);
-        const int32_t a1 = r0 + (int32_t)((int64_t)nr * (sb + 1) / nsub);
+    const uint32_t ntasks = (uint32_t)(ngroups * nsub);
+    // 32-bit arithmetic: nr * nsub < 2^27
+    for (uint32_t task = tid; task < ntasks; task += nthreads) {
+        const uint32_t g = task % (uint32_t)ngroups, sb = task / (uint32_t)ngroups;
+        const int32_t a0 = r0 + (int32_t)(((uint32_t)nr * sb) / (uint32_t)nsub);
+        const int32_t a1 = r0 + (int32_t)(((uint32_t)nr * (sb + 1)) / (uint32_t)nsub);
         if (a1 > a0)
-            run_task<K, HIST, CODES>(im, hw, g, a0, a1, cy);
+            run_task<K, HIST, CODES>(im, hw, (int32_t)g, a0, a1, cy);
     }
 }
 
