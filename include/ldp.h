@@ -122,12 +122,13 @@ typedef struct ldp_image_desc {
 #define LDP_MAX_SIZE_CLASSES 4
 typedef struct ldp_size_class {
     int64_t max_pixels;         /* upper bound of H*W for the class */
-    int32_t cell_rows_per_item; /* cell rows of one image per work item, >= 1 */
+    int32_t cell_rows_per_item; /* cell rows of one image per work item, >= 1 (at most
+                                   65536 / ((cells_x + 1) * 1024): its histograms sit in LDS) */
     int32_t rows_per_task;      /* target code rows per lane task, >= 1 */
 } ldp_size_class;
 
 typedef struct ldp_tune {
-    int32_t block_threads; /* threads per workgroup: 256, 512 or 1024 */
+    int32_t block_threads; /* threads per workgroup: a multiple of 64, 64..1024 (default 256) */
     int32_t grid_blocks;   /* persistent workgroups; 0 = fill the device */
     int32_t n_classes;     /* 0 (one default class) .. LDP_MAX_SIZE_CLASSES */
     int32_t reserved;

@@ -9,6 +9,11 @@ amortise the three-row prologue of each task).  This module times candidate
 choices on the caller's own device-resident batch by coordinate descent and
 keeps the winners in a JSON cache keyed by GPU architecture, k, cell grid and
 a coarse signature of the image size distribution.
+
+Timings are taken on a warmed-up device (the clocks ramp up under sustained
+load), each as the best of a few rounds, and the leading candidates are timed
+again interleaved before the winner is chosen, so the order in which
+candidates are tried does not decide the result.
 """
 import json
 import os
@@ -19,7 +24,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(_HERE, "tuned.json")
 
-THREADS = (256, 512, 1024)
+THREADS = tuple(range(128, 1025, 64))  # whole waves
 ROWS_PER_TASK = (4, 8, 16, 32)
 
 
@@ -69,7 +74,8 @@ def default_classes(Hs, Ws, cells_y):
             dict(cell_rows_per_item=1, rows_per_task=8)]
 
 
-def _time_plan(binding, descs, n, pixels, k, cells, tune, reps=5):
+def _time_plan(binding, descs, n, pixels, k, cells, tune, reps=8, rounds=3):
+    """Best mean launch time (ms) over `rounds` rounds of `reps` launches."""
     import torch
     plan = binding.BatchPlan(n, pixels, k, cells[0], cells[1], tune)
     try:
@@ -77,14 +83,32 @@ def _time_plan(binding, descs, n, pixels, k, cells, tune, reps=5):
         for _ in range(2):
             plan.run()
         torch.cuda.synchronize()
+        best = float("inf")
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(reps):
-            plan.run()
-        e1.record()
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / reps
+        for _ in range(rounds):
+            e0.record()
+            for _ in range(reps):
+                plan.run()
+            e1.record()
+            torch.cuda.synchronize()
+            best = min(best, e0.elapsed_time(e1) / reps)
+        return best
+    finally:
+        plan.close()
+
+
+def _warm_up(binding, descs, n, pixels, k, cells, tune, seconds=0.3):
+    """Keep the device busy with this batch for about `seconds`."""
+    import torch
+    plan = binding.BatchPlan(n, pixels, k, cells[0], cells[1], tune)
+    try:
+        plan.set(descs)
+        t_end = time.time() + seconds
+        while time.time() < t_end:
+            for _ in range(10):
+                plan.run()
+            torch.cuda.synchronize()
     finally:
         plan.close()
 
@@ -97,6 +121,7 @@ def tune_batch(descs, Hs, Ws, k, cells, budget_s=60.0, verbose=False):
     pixels = int((np.asarray(Hs, dtype=np.int64) * np.asarray(Ws, dtype=np.int64)).sum())
     t_end = time.time() + budget_s
     best = dict(block_threads=256, classes=default_classes(Hs, Ws, cells[0]))
+    _warm_up(binding, descs, n, pixels, k, cells, best)
     best_ms = _time_plan(binding, descs, n, pixels, k, cells, best)
     seen = {json.dumps(best, sort_keys=True): best_ms}
 
@@ -128,7 +153,19 @@ def tune_batch(descs, Hs, Ws, k, cells, budget_s=60.0, verbose=False):
                 cls = [dict(c) for c in best["classes"]]
                 cls[ci]["rows_per_task"] = rpt
                 attempt(dict(best, classes=cls))
-    return best, best_ms
+
+    # time the leading candidates again, interleaved, and keep the best
+    lead = sorted(seen.items(), key=lambda kv: kv[1])[:4]
+    again = {s: float("inf") for s, _ in lead}
+    for _ in range(3):
+        for s in again:
+            ms = _time_plan(binding, descs, n, pixels, k, cells, json.loads(s))
+            again[s] = min(again[s], ms)
+    s_best = min(again, key=again.get)
+    if verbose:
+        for s, ms in sorted(again.items(), key=lambda kv: kv[1]):
+            print("  again %.4f ms %s" % (ms, s), flush=True)
+    return json.loads(s_best), again[s_best]
 
 
 def save(Hs, Ws, k, cells, tune, ms, path=CACHE, note=""):

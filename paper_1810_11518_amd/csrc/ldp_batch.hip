@@ -160,10 +160,15 @@ int ldp_batch_plan_create(ldp_batch_plan **out, int32_t max_images, int64_t max_
             }
         }
     }
-    if ((p->threads != 256 && p->threads != 512 && p->threads != 1024) || p->grid < 0) {
+    // any whole number of waves: the lane tasks of a cell row are spread over
+    // the workgroup's threads, whatever their count
+    if (p->threads < 64 || p->threads > 1024 || p->threads % 64 != 0 || p->grid < 0) {
         delete p;
         return LDP_ERR_INVALID_ARG;
     }
+    // an item's cell rows of histograms must fit in 64 KB of LDS (cells_x <= 63
+    // leaves room for at least one)
+    const int32_t lds_cpi = (int32_t)(65536u / ldp::hist_row_bytes(cells_x));
     int32_t max_cpi = 1, min_cpi = cells_y;
     for (int c = 0; c < p->n_classes; ++c) {
         ldp_size_class &sc = p->classes[c];
@@ -171,18 +176,14 @@ int ldp_batch_plan_create(ldp_batch_plan **out, int32_t max_images, int64_t max_
             delete p;
             return LDP_ERR_INVALID_ARG;
         }
-        sc.cell_rows_per_item = std::min(sc.cell_rows_per_item, cells_y);
+        sc.cell_rows_per_item = std::min(std::min(sc.cell_rows_per_item, cells_y), lds_cpi);
         max_cpi = std::max(max_cpi, sc.cell_rows_per_item);
         min_cpi = std::min(min_cpi, sc.cell_rows_per_item);
     }
     p->classes[p->n_classes - 1].max_pixels = INT64_MAX;
     p->max_items = (int64_t)max_images * ((cells_y + min_cpi - 1) / min_cpi);
-    // LDS: the largest item's cell rows plus the discard cell
-    p->lds_bytes = (size_t)(max_cpi * cells_x + 1) * 256 * sizeof(uint32_t);
-    if (p->lds_bytes > 64 * 1024) {
-        delete p;
-        return LDP_ERR_UNSUPPORTED;
-    }
+    // LDS: the largest item's cell rows, each with its discard cell
+    p->lds_bytes = (size_t)max_cpi * ldp::hist_row_bytes(cells_x);
     if (hipGetDevice(&p->device) != hipSuccess) {
         delete p;
         return LDP_ERR_HIP;

@@ -45,6 +45,21 @@ __device__ __forceinline__ uint32_t U(u16x2 v) { return __builtin_bit_cast(uint3
 __device__ __forceinline__ u16x2 vmax(u16x2 a, u16x2 b) { return __builtin_elementwise_max(a, b); }
 __device__ __forceinline__ u16x2 vmin(u16x2 a, u16x2 b) { return __builtin_elementwise_min(a, b); }
 
+// Maximum of three, one instruction (v_pk_maximum3_f16).  The fields are
+// compared as f16: a 16-bit pattern below 0x7C00 with the sign bit clear is a
+// finite non-negative f16 (zero, denormal or normal), and such values are
+// ordered exactly as their patterns, so the f16 maximum of sums <= 765 is
+// their integer maximum.  The kernels keep f16 denormals (the default mode),
+// and IEEE maximum returns one of its operands unchanged.
+typedef _Float16 h16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ u16x2 vmax3(u16x2 a, u16x2 b, u16x2 c)
+{
+    const h16x2 r = __builtin_elementwise_maximum(
+        __builtin_elementwise_maximum(__builtin_bit_cast(h16x2, a), __builtin_bit_cast(h16x2, b)),
+        __builtin_bit_cast(h16x2, c));
+    return __builtin_bit_cast(u16x2, r);
+}
+
 // ------------------------------------------------------------ k-th largest
 // Eq. 2's m_k: the k-th element of the eight values in descending order,
 // duplicates kept.  Split into halves A = s0..s3 and B = s4..s7; the k-th
@@ -84,7 +99,7 @@ __device__ __forceinline__ u16x2 kth_largest(const u16x2 (&s)[8])
         u16x2 g1 = vmax(s[6], s[7]), k1 = vmin(s[6], s[7]);
         u16x2 y1 = vmax(g0, g1), nh = vmin(g0, g1), nl = vmax(k0, k1);
         u16x2 y2 = vmax(nh, nl), y3 = vmin(nh, nl);
-        return vmax(vmax(x3, y3), vmax(vmin(x1, y2), vmin(x2, y1)));
+        return vmax3(x3, y3, vmax(vmin(x1, y2), vmin(x2, y1)));
     } else if constexpr (K == 2) {
         // m_2 = max(A_(2), B_(2), min(A_(1), B_(1)))
         u16x2 h0 = vmax(s[0], s[1]), l0 = vmin(s[0], s[1]);
@@ -93,10 +108,9 @@ __device__ __forceinline__ u16x2 kth_largest(const u16x2 (&s)[8])
         u16x2 g0 = vmax(s[4], s[5]), k0 = vmin(s[4], s[5]);
         u16x2 g1 = vmax(s[6], s[7]), k1 = vmin(s[6], s[7]);
         u16x2 y1 = vmax(g0, g1), y2 = vmax(vmin(g0, g1), vmax(k0, k1));
-        return vmax(vmax(x2, y2), vmin(x1, y1));
+        return vmax3(x2, y2, vmin(x1, y1));
     } else if constexpr (K == 1) {
-        return vmax(vmax(vmax(s[0], s[1]), vmax(s[2], s[3])),
-                    vmax(vmax(s[4], s[5]), vmax(s[6], s[7])));
+        return vmax3(vmax3(s[0], s[1], s[2]), vmax3(s[3], s[4], s[5]), vmax(s[6], s[7]));
     } else {
         Sorted4 A = sort4(s[0], s[1], s[2], s[3]);
         Sorted4 B = sort4(s[4], s[5], s[6], s[7]);

@@ -11,6 +11,11 @@
 // same values, the columns it shares with the previous group; its first
 // 8 - n columns go to a discard bin of the histogram so every pixel is
 // counted once).  Only code maps narrower than 8 columns take a masked path.
+//
+// A work item (one workgroup at a time) is a range of code rows covering
+// whole cell rows (or part of one); its histogram cells live in LDS.  Every
+// lane keeps one column group and one row band of each cell row for the whole
+// item, so the per-pixel cell lookup is done once per item.
 #pragma once
 #include "ldp_device.hpp"
 
@@ -56,14 +61,12 @@ __host__ __device__ __forceinline__ int32_t cell_start(int32_t c, int32_t n, int
     return (int32_t)(((uint32_t)c * (uint32_t)n + (uint32_t)cells - 1u) / (uint32_t)cells);
 }
 
-// LDS histogram window: cell rows [cy0, cy0 + ncy) x cells_x cells of 256
-// uint32 bins at byte ((cy - cy0)*cells_x + cx)*1024, then one discard cell.
-struct HistWin {
-    uint32_t *lds;
-    int32_t cells_y, cells_x;
-    int32_t cy0, ncy;
-    __device__ uint32_t discard() const { return (uint32_t)(ncy * cells_x) * 1024u; }
-};
+// LDS histogram window of a work item: per cell row, cells_x cells of 256
+// uint32 bins followed by one discard cell (pixels that another lane counts).
+__host__ __device__ __forceinline__ uint32_t hist_row_bytes(int32_t cells_x)
+{
+    return (uint32_t)(cells_x + 1) * 1024u;
+}
 
 // Loads one image row for the lane: 16 bytes from the 4-aligned offset at or
 // below the lane's first byte (aligned dwords never leave the image's last
@@ -86,18 +89,61 @@ __device__ __forceinline__ void unpack_raw(Row &r, const RawRow &rr)
     make_row(r, u0, u1, u2);
 }
 
+// Column group of a lane: its first code column (groups of 8, the last one
+// ends at Wc - 1) and the histogram cell column of each pixel, one byte per
+// pixel (bytes 0..3 of cl for pixels 0..3, of ch for 4..7); the discard cell
+// (cells_x) for the leading columns the previous group counts.
+struct Cols {
+    int32_t j0;
+    uint32_t cl, ch;
+    bool uniform_cell;  // all 8 pixels counted in one cell
+};
+
+template <bool HIST>
+__device__ __forceinline__ Cols group_cols(const ImgView &im, int32_t cells_x, int32_t g)
+{
+    Cols c;
+    c.j0 = min(8 * g, im.Wc - 8);
+    c.cl = c.ch = 0;
+    c.uniform_cell = false;
+    if constexpr (HIST) {
+        const int32_t skip = 8 * g - c.j0;
+#pragma unroll
+        for (int p = 0; p < 8; ++p) {
+            const uint32_t cx = ((uint32_t)(c.j0 + p) * (uint32_t)cells_x) / (uint32_t)im.Wc;
+            const uint32_t d = (p < skip ? (uint32_t)cells_x : cx) << (8 * (p & 3));
+            if (p < 4)
+                c.cl |= d;
+            else
+                c.ch |= d;
+        }
+        c.uniform_cell = c.cl == c.ch && c.cl == __builtin_amdgcn_alignbyte(c.cl, c.cl, 1);
+    }
+    return c;
+}
+
 // Per-task state of the row walk.
 struct Walk {
     uint32_t off, last_off;  // image byte offset of the prefetched / last row
     uint32_t coff;           // code byte offset of the current code row
-    uint32_t cb[8];          // histogram byte base of each pixel's cell
-    bool uniform_cell;       // all 8 pixels counted in one cell
+    uint32_t rowb;           // LDS byte offset of the cell row's histograms
+    uint32_t cl, ch;         // per-pixel cell columns (Cols)
+    bool uniform_cell;
 };
+
+// LDS byte address of the bin of pixel q (0..3) of the code word x whose
+// cell bytes are d: ((cell << 8) | code) * 4 past the cell row.
+__device__ __forceinline__ uint32_t bin_addr(uint32_t x, uint32_t d, int q, uint32_t rowb)
+{
+    // byte 0 = code byte q of x, byte 1 = cell byte q of d, bytes 2, 3 = 0
+    const uint32_t sel = (uint32_t)q | ((uint32_t)(4 + q) << 8) | 0x0C0C0000u;
+    return (__builtin_amdgcn_perm(d, x, sel) << 2) + rowb;
+}
 
 // One code row: the next image row arrives in `raw` and becomes `b`; t and m
 // are the two rows above; Vt = X_t + X_m.  Writes Vb = X_m + X_b.
 template <int K, bool HIST, bool CODES>
-__device__ __forceinline__ void step(const ImgView &im, const HistWin &hw, Walk &w, RawRow &raw,
+__device__ __forceinline__ void step(const ImgView &im, uint32_t *lds_bins, Walk &w, RawRow &raw,
                                      const Row &t, const Row &m, Row &b, const uint32_t (&Vt)[6],
                                      uint32_t (&Vb)[6])
 {
@@ -116,45 +162,35 @@ __device__ __forceinline__ void step(const ImgView &im, const HistWin &hw, Walk 
         w.coff += (uint32_t)im.Wc;
     }
     if constexpr (HIST) {
-        char *lds = reinterpret_cast<char *>(hw.lds);
+        char *lds = reinterpret_cast<char *>(lds_bins);
         if (w.uniform_cell && lo == hi && lo == __builtin_amdgcn_alignbyte(lo, lo, 1)) {
             // eight equal codes in one cell (flat regions): one update
-            atomicAdd(reinterpret_cast<uint32_t *>(lds + (w.cb[0] | ((lo & 0xFFu) << 2))), 8u);
+            atomicAdd(reinterpret_cast<uint32_t *>(lds + bin_addr(lo, w.cl, 0, w.rowb)), 8u);
         } else {
 #pragma unroll
             for (int p = 0; p < 8; ++p) {
-                const uint32_t x = p < 4 ? lo : hi;
-                const int q = p & 3;
-                const uint32_t sh = q == 0 ? (x << 2) : (x >> (8 * q - 2));
-                // (sh & 0x3FC) | cb[p]: cell bases are multiples of 1024
-                const uint32_t addr = __builtin_amdgcn_bitop3_b32(sh, 0x3FCu, w.cb[p], 0xEA);
+                const uint32_t addr = p < 4 ? bin_addr(lo, w.cl, p, w.rowb)
+                                            : bin_addr(hi, w.ch, p - 4, w.rowb);
                 atomicAdd(reinterpret_cast<uint32_t *>(lds + addr), 1u);
             }
         }
     }
 }
 
-// Run the code rows [r0, r1) of column group g; they all lie in cell row cy.
+// Run code rows [r0, r1) of the column group `c`; with HIST they all lie in
+// the cell row whose histograms start at LDS byte `rowb`.
 template <int K, bool HIST, bool CODES>
-__device__ __forceinline__ void run_task(const ImgView &im, const HistWin &hw, int32_t g,
-                                         int32_t r0, int32_t r1, int32_t cy)
+__device__ __forceinline__ void run_task(const ImgView &im, uint32_t *lds_bins, uint32_t rowb,
+                                         const Cols &c, int32_t r0, int32_t r1)
 {
-    // first code column of the lane: groups of 8, the last one ends at Wc - 1
-    const int32_t j0 = min(8 * g, im.Wc - 8);
-    const int32_t skip = 8 * g - j0;  // leading columns the previous group counts
     Walk w;
-    w.off = im.off0 + (uint32_t)r0 * im.stride + (uint32_t)j0;
-    w.last_off = im.off0 + (uint32_t)(im.H - 1) * im.stride + (uint32_t)j0;
-    w.coff = (uint32_t)r0 * (uint32_t)im.Wc + (uint32_t)j0;
-    if constexpr (HIST) {
-        const uint32_t rowb = (uint32_t)((cy - hw.cy0) * hw.cells_x) * 1024u;
-#pragma unroll
-        for (int p = 0; p < 8; ++p) {
-            const uint32_t cx = ((uint32_t)(j0 + p) * (uint32_t)hw.cells_x) / (uint32_t)im.Wc;
-            w.cb[p] = p < skip ? hw.discard() : rowb + cx * 1024u;
-        }
-        w.uniform_cell = skip == 0 && w.cb[0] == w.cb[7];
-    }
+    w.off = im.off0 + (uint32_t)r0 * im.stride + (uint32_t)c.j0;
+    w.last_off = im.off0 + (uint32_t)(im.H - 1) * im.stride + (uint32_t)c.j0;
+    w.coff = (uint32_t)r0 * (uint32_t)im.Wc + (uint32_t)c.j0;
+    w.rowb = rowb;
+    w.cl = c.cl;
+    w.ch = c.ch;
+    w.uniform_cell = c.uniform_cell;
     RawRow raw;
     Row A, B, C;
     uint32_t VAB[6], VBC[6], VCA[6];
@@ -173,7 +209,7 @@ __device__ __forceinline__ void run_task(const ImgView &im, const HistWin &hw, i
     int32_t n = r1 - r0;
 #ifdef LDP_ROLLED_ROWS
     for (; n > 0; --n) {
-        step<K, HIST, CODES>(im, hw, w, raw, A, B, C, VAB, VBC);
+        step<K, HIST, CODES>(im, lds_bins, w, raw, A, B, C, VAB, VBC);
         A = B;
         B = C;
 #pragma unroll
@@ -183,22 +219,22 @@ __device__ __forceinline__ void run_task(const ImgView &im, const HistWin &hw, i
     (void)VCA;
 #else
     for (; n >= 3; n -= 3) {
-        step<K, HIST, CODES>(im, hw, w, raw, A, B, C, VAB, VBC);
-        step<K, HIST, CODES>(im, hw, w, raw, B, C, A, VBC, VCA);
-        step<K, HIST, CODES>(im, hw, w, raw, C, A, B, VCA, VAB);
+        step<K, HIST, CODES>(im, lds_bins, w, raw, A, B, C, VAB, VBC);
+        step<K, HIST, CODES>(im, lds_bins, w, raw, B, C, A, VBC, VCA);
+        step<K, HIST, CODES>(im, lds_bins, w, raw, C, A, B, VCA, VAB);
     }
     if (n >= 1)
-        step<K, HIST, CODES>(im, hw, w, raw, A, B, C, VAB, VBC);
+        step<K, HIST, CODES>(im, lds_bins, w, raw, A, B, C, VAB, VBC);
     if (n >= 2)
-        step<K, HIST, CODES>(im, hw, w, raw, B, C, A, VBC, VCA);
+        step<K, HIST, CODES>(im, lds_bins, w, raw, B, C, A, VBC, VCA);
 #endif
 }
 
 // Code rows [r0, r1) of a code map narrower than 8 columns: one lane, the
-// pixels past the map masked.
+// pixels past the map masked (counted in the discard cell).
 template <int K, bool HIST, bool CODES>
-__device__ void run_task_narrow(const ImgView &im, const HistWin &hw, int32_t r0, int32_t r1,
-                                int32_t cy)
+__device__ void run_task_narrow(const ImgView &im, uint32_t *lds_bins, uint32_t rowb,
+                                int32_t cells_x, int32_t r0, int32_t r1)
 {
     const int nvalid = im.Wc;
     const uint32_t off = im.off0 + (uint32_t)r0 * im.stride;
@@ -214,10 +250,10 @@ __device__ void run_task_narrow(const ImgView &im, const HistWin &hw, int32_t r0
         Vt[a] = t.X[a] + m.X[a];
     uint32_t cb[8];
     if constexpr (HIST) {
-        const uint32_t rowb = (uint32_t)((cy - hw.cy0) * hw.cells_x) * 1024u;
         for (int p = 0; p < 8; ++p) {
-            uint32_t cx = (uint32_t)(((int64_t)min(p, im.Wc - 1) * hw.cells_x) / im.Wc);
-            cb[p] = p < nvalid ? rowb + cx * 1024u : hw.discard();
+            const uint32_t cx =
+                p < nvalid ? ((uint32_t)p * (uint32_t)cells_x) / (uint32_t)im.Wc : (uint32_t)cells_x;
+            cb[p] = rowb + cx * 1024u;
         }
     }
     for (int32_t r = r0; r < r1; ++r) {
@@ -235,7 +271,7 @@ __device__ void run_task_narrow(const ImgView &im, const HistWin &hw, int32_t r0
                                                      im.crsrc, (int)(coff + p), 0, 0);
         }
         if constexpr (HIST) {
-            char *lds = reinterpret_cast<char *>(hw.lds);
+            char *lds = reinterpret_cast<char *>(lds_bins);
             for (int p = 0; p < 8; ++p) {
                 const uint32_t code = ((p < 4 ? lo : hi) >> (8 * (p & 3))) & 0xFFu;
                 atomicAdd(reinterpret_cast<uint32_t *>(lds + (cb[p] | (code << 2))), 1u);
@@ -249,46 +285,16 @@ __device__ void run_task_narrow(const ImgView &im, const HistWin &hw, int32_t r0
     }
 }
 
-// Split the code rows [r0, r1) of cell row cy among the workgroup's threads:
-// task = (row sub-band, column group).
-template <int K, bool HIST, bool CODES>
-__device__ __forceinline__ void run_rows(const ImgView &im, const HistWin &hw, int32_t r0,
-                                         int32_t r1, int32_t cy, int32_t min_task_rows)
-{
-    const int tid = threadIdx.x, nthreads = blockDim.x;
-    const int32_t nr = r1 - r0;
-    if (nr <= 0)
-        return;
-    if (im.Wc < 8) {
-        const int32_t nsub = min(nthreads, nr);
-        if (tid < nsub) {
-            const int32_t a0 = r0 + (int32_t)(((uint32_t)nr * tid) / (uint32_t)nsub);
-            const int32_t a1 = r0 + (int32_t)(((uint32_t)nr * (tid + 1)) / (uint32_t)nsub);
-            if (a1 > a0)
-                run_task_narrow<K, HIST, CODES>(im, hw, a0, a1, cy);
-        }
-        return;
-    }
-    const int32_t ngroups = (im.Wc + 7) / 8;
-    // row sub-bands per column group: as many as the threads allow, but no
-    // shorter than min_task_rows code rows
-    const int32_t nsub =
-        max(1, min(nthreads / ngroups, (nr + min_task_rows - 1) / min_task_rows));
-    const uint32_t ntasks = (uint32_t)(ngroups * nsub);
-    // 32-bit arithmetic: nr * nsub < 2^27
-    for (uint32_t task = tid; task < ntasks; task += nthreads) {
-        const uint32_t g = task % (uint32_t)ngroups, sb = task / (uint32_t)ngroups;
-        const int32_t a0 = r0 + (int32_t)(((uint32_t)nr * sb) / (uint32_t)nsub);
-        const int32_t a1 = r0 + (int32_t)(((uint32_t)nr * (sb + 1)) / (uint32_t)nsub);
-        if (a1 > a0)
-            run_task<K, HIST, CODES>(im, hw, (int32_t)g, a0, a1, cy);
-    }
-}
-
 // ---------------------------------------------------------------- work items
 // One workgroup per work item: code rows [r0, r1) of cell rows [cy0, cy1).
 // When r0/r1 cut a cell row (an image split across workgroups) the flush adds
 // atomically into a zeroed histogram; otherwise it stores.
+//
+// Work split: a task is (row band, column group) of one cell row.  With at
+// most as many tasks per cell row as threads, lane tid keeps column group
+// tid % ngroups and row band tid / ngroups in every cell row of the item
+// (row bands no shorter than min_task_rows, as many as the threads allow).
+// Wider maps (more column groups than threads) take whole cell rows per task.
 template <int K, bool CODES>
 __device__ __forceinline__ void fused_item(const ImgView &im, uint32_t *lds, int32_t cells_y,
                                            int32_t cells_x, int32_t cy0, int32_t cy1, int32_t r0,
@@ -296,24 +302,74 @@ __device__ __forceinline__ void fused_item(const ImgView &im, uint32_t *lds, int
                                            int32_t min_task_rows)
 {
     const int tid = threadIdx.x, nthreads = blockDim.x;
-    const int32_t nbins = (cy1 - cy0) * cells_x * 256;
-    for (int32_t i = tid; i < nbins + 256; i += nthreads)
+    const uint32_t row_bytes = hist_row_bytes(cells_x);
+    const int32_t row_words = (cells_x + 1) * 256;
+    for (int32_t i = tid; i < (cy1 - cy0) * row_words; i += nthreads)
         lds[i] = 0;
     __syncthreads();
-    const HistWin hw{lds, cells_y, cells_x, cy0, cy1 - cy0};
-    for (int32_t cy = cy0; cy < cy1; ++cy) {
-        const int32_t a0 = max(r0, cell_start(cy, im.Hc, cells_y));
-        const int32_t a1 = min(r1, cell_start(cy + 1, im.Hc, cells_y));
-        run_rows<K, true, CODES>(im, hw, a0, a1, cy, min_task_rows);
+    // code rows [a, b) of the current cell row inside [r0, r1)
+    int32_t a = max(r0, cell_start(cy0, im.Hc, cells_y));
+    int32_t b = min(r1, cell_start(cy0 + 1, im.Hc, cells_y));
+    if (im.Wc < 8) {
+        for (int32_t cy = cy0; cy < cy1; ++cy) {
+            if (cy > cy0) {
+                a = b;
+                b = min(r1, cell_start(cy + 1, im.Hc, cells_y));
+            }
+            const int32_t nr = b - a, nsub = min(nthreads, nr);
+            if (tid < nsub) {
+                const int32_t a0 = a + (int32_t)(((uint32_t)nr * tid) / (uint32_t)nsub);
+                const int32_t a1 = a + (int32_t)(((uint32_t)nr * (tid + 1)) / (uint32_t)nsub);
+                if (a1 > a0)
+                    run_task_narrow<K, true, CODES>(im, lds, (cy - cy0) * row_bytes, cells_x,
+                                                    a0, a1);
+            }
+        }
+    } else {
+        const int32_t ngroups = (im.Wc + 7) / 8;
+        const int32_t nsub =
+            max(1, min(nthreads / ngroups, (b - a + min_task_rows - 1) / min_task_rows));
+        if (ngroups * nsub <= nthreads) {
+            if (tid < ngroups * nsub) {
+                const uint32_t g = (uint32_t)tid % (uint32_t)ngroups;
+                const uint32_t sb = (uint32_t)tid / (uint32_t)ngroups;
+                const Cols c = group_cols<true>(im, cells_x, (int32_t)g);
+                for (int32_t cy = cy0; cy < cy1; ++cy) {
+                    if (cy > cy0) {
+                        a = b;
+                        b = min(r1, cell_start(cy + 1, im.Hc, cells_y));
+                    }
+                    // 32-bit arithmetic: nr * nsub < 2^26
+                    const uint32_t nr = (uint32_t)max(b - a, 0);
+                    const int32_t a0 = a + (int32_t)((nr * sb) / (uint32_t)nsub);
+                    const int32_t a1 = a + (int32_t)((nr * (sb + 1)) / (uint32_t)nsub);
+                    if (a1 > a0)
+                        run_task<K, true, CODES>(im, lds, (cy - cy0) * row_bytes, c, a0, a1);
+                }
+            }
+        } else {
+            for (int32_t cy = cy0; cy < cy1; ++cy) {
+                if (cy > cy0) {
+                    a = b;
+                    b = min(r1, cell_start(cy + 1, im.Hc, cells_y));
+                }
+                for (int32_t g = tid; g < ngroups; g += nthreads)
+                    run_task<K, true, CODES>(im, lds, (cy - cy0) * row_bytes,
+                                             group_cols<true>(im, cells_x, g), a, b);
+            }
+        }
     }
     __syncthreads();
-    uint32_t *dst = hist + (int64_t)cy0 * cells_x * 256;
-    for (int32_t i = tid; i < nbins; i += nthreads) {
-        const uint32_t v = lds[i];
-        if (!atomic_flush)
-            dst[i] = v;
-        else if (v)
-            atomicAdd(dst + i, v);
+    for (int32_t r = 0; r < cy1 - cy0; ++r) {
+        const uint32_t *src = lds + r * row_words;
+        uint32_t *dst = hist + (int64_t)(cy0 + r) * cells_x * 256;
+        for (int32_t i = tid; i < cells_x * 256; i += nthreads) {
+            const uint32_t v = src[i];
+            if (!atomic_flush)
+                dst[i] = v;
+            else if (v)
+                atomicAdd(dst + i, v);
+        }
     }
 }
 

@@ -35,11 +35,10 @@ __global__ void __launch_bounds__(256) LDP_CODES_ATTR codes_kernel(const uint8_t
     const int32_t band = task / ngroups;
     const int32_t r0 = band * band_rows;
     const int32_t r1 = min(r0 + band_rows, im.Hc);
-    const HistWin hw{};
     if (im.Wc < 8)
-        run_task_narrow<K, false, true>(im, hw, r0, r1, 0);
+        run_task_narrow<K, false, true>(im, nullptr, 0, 0, r0, r1);
     else
-        run_task<K, false, true>(im, hw, g, r0, r1, 0);
+        run_task<K, false, true>(im, nullptr, 0, group_cols<false>(im, 0, g), r0, r1);
 }
 
 // ---------------------------------------------------------------- histograms
@@ -177,8 +176,8 @@ int launch_histograms(const uint8_t *codes, int32_t H, int32_t W, int32_t cells_
     return hipGetLastError() == hipSuccess ? LDP_OK : LDP_ERR_HIP;
 }
 
-// LDS bytes of one cell row of histograms plus the discard cell
-static size_t fused_lds_bytes(int32_t cells_x) { return (size_t)(cells_x + 1) * 256 * 4; }
+// LDS bytes of one cell row of histograms plus its discard cell
+static size_t fused_lds_bytes(int32_t cells_x) { return hist_row_bytes(cells_x); }
 
 int launch_extract(const uint8_t *img, int32_t H, int32_t W, int64_t stride, int32_t k,
                    int32_t cells_y, int32_t cells_x, uint8_t *codes, uint32_t *hist,

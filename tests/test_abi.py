@@ -60,8 +60,9 @@ def test_invalid_arguments_return_before_any_launch(lib):
     assert lib.ldp_batch_plan_create(ctypes.byref(plan), 0, 100, 3, 7, 6, None) == E
     assert lib.ldp_batch_plan_create(ctypes.byref(plan), 10, 100, 9, 7, 6, None) == E
     assert lib.ldp_batch_plan_create(ctypes.byref(plan), 10, 100, 3, 7, 200, None) == E
-    t = binding.make_tune(dict(block_threads=300))
-    assert lib.ldp_batch_plan_create(ctypes.byref(plan), 10, 100, 3, 7, 6, ctypes.byref(t)) == E
+    for th in (300, 32, 1088):  # not a whole number of waves, or above 1024
+        t = binding.make_tune(dict(block_threads=th))
+        assert lib.ldp_batch_plan_create(ctypes.byref(plan), 10, 100, 3, 7, 6, ctypes.byref(t)) == E
     assert lib.ldp_batch_run(None, None) == E
     srv = ctypes.c_void_p()
     bad = binding.ServerConfig(0, 1, 1, 1, 3, 7, 6, 1, 0)

@@ -83,6 +83,9 @@ def test_uneven_batch_matches_oracle(lib, k):
     dict(block_threads=256), dict(block_threads=1024, classes=[dict(rows_per_task=16)]),
     dict(block_threads=512, classes=[dict(cell_rows_per_item=3)]),
     dict(grid_blocks=5, classes=[dict(cell_rows_per_item=7)]),
+    dict(block_threads=64, classes=[dict(rows_per_task=3)]),
+    dict(block_threads=320, classes=[dict(cell_rows_per_item=2)]),
+    dict(block_threads=448, grid_blocks=37, classes=[dict(cell_rows_per_item=4, rows_per_task=5)]),
     dict(block_threads=512, classes=[dict(max_pixels=20000, cell_rows_per_item=7, rows_per_task=2),
                                      dict(max_pixels=60000, cell_rows_per_item=2, rows_per_task=4),
                                      dict(cell_rows_per_item=1, rows_per_task=32)])])

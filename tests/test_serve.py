@@ -94,8 +94,10 @@ def test_invalid_requests_are_refused():
 
 def test_arrivals_during_running_batches_are_admitted_then():
     """Continuous batching: a request arriving while a batch runs is admitted
-    into another launch slot before that batch completes."""
-    srv = binding.Server(1 << 24, 64, 4, 3, 3, 7, 6, dry_run=True, dry_run_us=50000)
+    into another launch slot before that batch completes.  Eight slots: the
+    four first requests take at most four launches however the dispatcher
+    groups them, so a slot is always free for the late one."""
+    srv = binding.Server(1 << 24, 64, 4, 8, 3, 7, 6, dry_run=True, dry_run_us=50000)
     first = [srv.submit(*_req(64, 64)) for _ in range(4)]
     time.sleep(0.01)
     later = srv.submit(*_req(64, 64))
