@@ -45,19 +45,24 @@ __device__ __forceinline__ uint32_t U(u16x2 v) { return __builtin_bit_cast(uint3
 __device__ __forceinline__ u16x2 vmax(u16x2 a, u16x2 b) { return __builtin_elementwise_max(a, b); }
 __device__ __forceinline__ u16x2 vmin(u16x2 a, u16x2 b) { return __builtin_elementwise_min(a, b); }
 
-// Maximum of three, one instruction (v_pk_maximum3_f16).  The fields are
-// compared as f16: a 16-bit pattern below 0x7C00 with the sign bit clear is a
-// finite non-negative f16 (zero, denormal or normal), and such values are
-// ordered exactly as their patterns, so the f16 maximum of sums <= 765 is
-// their integer maximum.  The kernels keep f16 denormals (the default mode),
-// and IEEE maximum returns one of its operands unchanged.
+// Maximum and minimum of three, one instruction each (v_pk_maximum3_f16,
+// v_pk_minimum3_f16).  The fields are compared as f16: a 16-bit pattern below
+// 0x7C00 with the sign bit clear is a finite non-negative f16 (zero, denormal
+// or normal), and such values are ordered exactly as their patterns, so the
+// f16 maximum / minimum of sums <= 765 is their integer maximum / minimum.
+// The kernels keep f16 denormals (the default mode), and IEEE maximum and
+// minimum return one of their operands unchanged.
 typedef _Float16 h16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ h16x2 H(u16x2 v) { return __builtin_bit_cast(h16x2, v); }
 __device__ __forceinline__ u16x2 vmax3(u16x2 a, u16x2 b, u16x2 c)
 {
-    const h16x2 r = __builtin_elementwise_maximum(
-        __builtin_elementwise_maximum(__builtin_bit_cast(h16x2, a), __builtin_bit_cast(h16x2, b)),
-        __builtin_bit_cast(h16x2, c));
-    return __builtin_bit_cast(u16x2, r);
+    return __builtin_bit_cast(
+        u16x2, __builtin_elementwise_maximum(__builtin_elementwise_maximum(H(a), H(b)), H(c)));
+}
+__device__ __forceinline__ u16x2 vmin3(u16x2 a, u16x2 b, u16x2 c)
+{
+    return __builtin_bit_cast(
+        u16x2, __builtin_elementwise_minimum(__builtin_elementwise_minimum(H(a), H(b)), H(c)));
 }
 
 // ------------------------------------------------------------ k-th largest
@@ -88,27 +93,30 @@ template <int K>
 __device__ __forceinline__ u16x2 kth_largest(const u16x2 (&s)[8])
 {
     static_assert(K >= 1 && K <= 8, "k in 1..8");
+    // Each half is sorted as two pairs: A_(1) = max(h0, h1), and the middle
+    // two of A are {mh, ml} = {min(h0, h1), max(l0, l1)} (A_(2) their max,
+    // A_(3) their min); likewise B with g, k, nh, nl.
     if constexpr (K == 3) {
-        // sorted top three of each half, then
-        // m_3 = max(A_(3), B_(3), min(A_(1), B_(2)), min(A_(2), B_(1)))
+        // m_3 = max(A_(3), B_(3), min(A_(1), B_(2)), min(A_(2), B_(1))); the
+        // last two terms together equal min(max(A_(2), B_(2)), A_(1), B_(1)),
+        // and max(A_(2), B_(2)) is the largest of mh, ml, nh, nl
         u16x2 h0 = vmax(s[0], s[1]), l0 = vmin(s[0], s[1]);
         u16x2 h1 = vmax(s[2], s[3]), l1 = vmin(s[2], s[3]);
         u16x2 x1 = vmax(h0, h1), mh = vmin(h0, h1), ml = vmax(l0, l1);
-        u16x2 x2 = vmax(mh, ml), x3 = vmin(mh, ml);
         u16x2 g0 = vmax(s[4], s[5]), k0 = vmin(s[4], s[5]);
         u16x2 g1 = vmax(s[6], s[7]), k1 = vmin(s[6], s[7]);
         u16x2 y1 = vmax(g0, g1), nh = vmin(g0, g1), nl = vmax(k0, k1);
-        u16x2 y2 = vmax(nh, nl), y3 = vmin(nh, nl);
-        return vmax3(x3, y3, vmax(vmin(x1, y2), vmin(x2, y1)));
+        u16x2 mid = vmin3(vmax3(mh, ml, vmax(nh, nl)), x1, y1);
+        return vmax3(vmin(mh, ml), vmin(nh, nl), mid);
     } else if constexpr (K == 2) {
         // m_2 = max(A_(2), B_(2), min(A_(1), B_(1)))
         u16x2 h0 = vmax(s[0], s[1]), l0 = vmin(s[0], s[1]);
         u16x2 h1 = vmax(s[2], s[3]), l1 = vmin(s[2], s[3]);
-        u16x2 x1 = vmax(h0, h1), x2 = vmax(vmin(h0, h1), vmax(l0, l1));
+        u16x2 x1 = vmax(h0, h1), mh = vmin(h0, h1), ml = vmax(l0, l1);
         u16x2 g0 = vmax(s[4], s[5]), k0 = vmin(s[4], s[5]);
         u16x2 g1 = vmax(s[6], s[7]), k1 = vmin(s[6], s[7]);
-        u16x2 y1 = vmax(g0, g1), y2 = vmax(vmin(g0, g1), vmax(k0, k1));
-        return vmax3(x2, y2, vmin(x1, y1));
+        u16x2 y1 = vmax(g0, g1), nh = vmin(g0, g1), nl = vmax(k0, k1);
+        return vmax3(mh, ml, vmax3(nh, nl, vmin(x1, y1)));
     } else if constexpr (K == 1) {
         return vmax3(vmax3(s[0], s[1], s[2]), vmax3(s[3], s[4], s[5]), vmax(s[6], s[7]));
     } else {
