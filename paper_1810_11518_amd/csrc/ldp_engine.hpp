@@ -290,10 +290,13 @@ __device__ void run_task_narrow(const ImgView &im, uint32_t *lds_bins, uint32_t 
 // When r0/r1 cut a cell row (an image split across workgroups) the flush adds
 // atomically into a zeroed histogram; otherwise it stores.
 //
-// Work split: a task is (row band, column group) of one cell row.  With at
-// most as many tasks per cell row as threads, lane tid keeps column group
-// tid % ngroups and row band tid / ngroups in every cell row of the item
-// (row bands no shorter than min_task_rows, as many as the threads allow).
+// Work split: a task is (row band, column group) of one cell row, and a lane
+// keeps the same task in every cell row of the item.  With q = threads /
+// ngroups >= 1, every column group gets q row bands (fewer if that would make
+// bands shorter than min_task_rows); the threads left over, threads - q *
+// ngroups, give as many groups one band more, so that no lane idles.  Lanes
+// [0, base) take the q-band groups, column group fastest (neighbouring lanes
+// read neighbouring columns), lanes [base, threads) the (q+1)-band groups.
 // Wider maps (more column groups than threads) take whole cell rows per task.
 template <int K, bool CODES>
 __device__ __forceinline__ void fused_item(const ImgView &im, uint32_t *lds, int32_t cells_y,
@@ -327,22 +330,34 @@ __device__ __forceinline__ void fused_item(const ImgView &im, uint32_t *lds, int
         }
     } else {
         const int32_t ngroups = (im.Wc + 7) / 8;
-        const int32_t nsub =
-            max(1, min(nthreads / ngroups, (b - a + min_task_rows - 1) / min_task_rows));
-        if (ngroups * nsub <= nthreads) {
-            if (tid < ngroups * nsub) {
-                const uint32_t g = (uint32_t)tid % (uint32_t)ngroups;
-                const uint32_t sb = (uint32_t)tid / (uint32_t)ngroups;
+        const int32_t q = nthreads / ngroups;
+        if (q >= 1) {
+            const int32_t cap = (b - a + min_task_rows - 1) / min_task_rows;
+            const int32_t nsub = max(1, min(q, cap));
+            // groups with one band more (only when bands stay long enough)
+            const int32_t nx = (nsub == q && cap > q) ? nthreads - q * ngroups : 0;
+            const int32_t base = nsub * (ngroups - nx);
+            if (tid < base + (nsub + 1) * nx) {
+                uint32_t g, sb, nb;
+                if (tid < base) {
+                    g = (uint32_t)tid % (uint32_t)(ngroups - nx);
+                    sb = (uint32_t)tid / (uint32_t)(ngroups - nx);
+                    nb = (uint32_t)nsub;
+                } else {
+                    g = (uint32_t)(ngroups - nx) + (uint32_t)(tid - base) % (uint32_t)nx;
+                    sb = (uint32_t)(tid - base) / (uint32_t)nx;
+                    nb = (uint32_t)nsub + 1;
+                }
                 const Cols c = group_cols<true>(im, cells_x, (int32_t)g);
                 for (int32_t cy = cy0; cy < cy1; ++cy) {
                     if (cy > cy0) {
                         a = b;
                         b = min(r1, cell_start(cy + 1, im.Hc, cells_y));
                     }
-                    // 32-bit arithmetic: nr * nsub < 2^26
+                    // 32-bit arithmetic: nr * nb <= 2^16 * 2^10
                     const uint32_t nr = (uint32_t)max(b - a, 0);
-                    const int32_t a0 = a + (int32_t)((nr * sb) / (uint32_t)nsub);
-                    const int32_t a1 = a + (int32_t)((nr * (sb + 1)) / (uint32_t)nsub);
+                    const int32_t a0 = a + (int32_t)((nr * sb) / nb);
+                    const int32_t a1 = a + (int32_t)((nr * (sb + 1)) / nb);
                     if (a1 > a0)
                         run_task<K, true, CODES>(im, lds, (cy - cy0) * row_bytes, c, a0, a1);
                 }
