@@ -67,69 +67,69 @@ __device__ __forceinline__ u16x2 vmin3(u16x2 a, u16x2 b, u16x2 c)
 
 // ------------------------------------------------------------ k-th largest
 // Eq. 2's m_k: the k-th element of the eight values in descending order,
-// duplicates kept.  Split into halves A = s0..s3 and B = s4..s7; the k-th
-// largest of A u B is max over i + j = k of min(A_(i), B_(j)), with
-// A_(0) = B_(0) = +infinity and A_(i) the i-th largest of A.
-
-struct Sorted4 {
-    u16x2 v[5];  // v[1] >= v[2] >= v[3] >= v[4]; v[0] = +inf
+// duplicates kept.  Split into halves A = s0..s3 and B = s4..s7, each sorted
+// as two pairs: A_(1) = max(h0, h1) is A's largest, {mh, ml} = {min(h0, h1),
+// max(l0, l1)} its middle two (A_(2) their max, A_(3) their min) and
+// min(l0, l1) its smallest; likewise B with g, k, nh, nl.  The k-th largest
+// of A u B is max over i + j = k of min(A_(i), B_(j)) (A_(0) = +infinity):
+//   k = 2: max(A_(2), B_(2), min(A_(1), B_(1)))
+//   k = 3: max(A_(3), B_(3), min(A_(1), B_(2)), min(A_(2), B_(1))), where the
+//          last two terms together equal min(max(A_(2), B_(2)), A_(1), B_(1))
+//   k = 4: max(A_(4), B_(4), min(A_(2), B_(2)), min(A_(1), B_(3)),
+//          min(A_(3), B_(1))), the last two equal to
+//          min(max(A_(3), B_(3)), A_(1), B_(1)).
+// The (9-k)-th largest is the k-th smallest: the same network with max and
+// min exchanged (k = 5, 6, 7 from 4, 3, 2).
+template <bool SMALLEST>
+struct Order {
+    static __device__ __forceinline__ u16x2 hi(u16x2 a, u16x2 b) { return SMALLEST ? vmin(a, b) : vmax(a, b); }
+    static __device__ __forceinline__ u16x2 lo(u16x2 a, u16x2 b) { return SMALLEST ? vmax(a, b) : vmin(a, b); }
+    static __device__ __forceinline__ u16x2 hi3(u16x2 a, u16x2 b, u16x2 c)
+    {
+        return SMALLEST ? vmin3(a, b, c) : vmax3(a, b, c);
+    }
+    static __device__ __forceinline__ u16x2 lo3(u16x2 a, u16x2 b, u16x2 c)
+    {
+        return SMALLEST ? vmax3(a, b, c) : vmin3(a, b, c);
+    }
 };
 
-__device__ __forceinline__ Sorted4 sort4(u16x2 a, u16x2 b, u16x2 c, u16x2 d)
+// k-th largest (SMALLEST = false) or k-th smallest (true) for k = 2, 3, 4
+template <int K, bool SMALLEST>
+__device__ __forceinline__ u16x2 kth_network(const u16x2 (&s)[8])
 {
-    u16x2 h0 = vmax(a, b), l0 = vmin(a, b);
-    u16x2 h1 = vmax(c, d), l1 = vmin(c, d);
-    Sorted4 s;
-    s.v[0] = V(0xFFFFFFFFu);
-    s.v[1] = vmax(h0, h1);
-    u16x2 mh = vmin(h0, h1), ml = vmax(l0, l1);
-    s.v[2] = vmax(mh, ml);
-    s.v[3] = vmin(mh, ml);
-    s.v[4] = vmin(l0, l1);
-    return s;
+    typedef Order<SMALLEST> O;
+    u16x2 h0 = O::hi(s[0], s[1]), l0 = O::lo(s[0], s[1]);
+    u16x2 h1 = O::hi(s[2], s[3]), l1 = O::lo(s[2], s[3]);
+    u16x2 g0 = O::hi(s[4], s[5]), k0 = O::lo(s[4], s[5]);
+    u16x2 g1 = O::hi(s[6], s[7]), k1 = O::lo(s[6], s[7]);
+    u16x2 x1 = O::hi(h0, h1), mh = O::lo(h0, h1), ml = O::hi(l0, l1);
+    u16x2 y1 = O::hi(g0, g1), nh = O::lo(g0, g1), nl = O::hi(k0, k1);
+    if constexpr (K == 2) {
+        return O::hi3(mh, ml, O::hi3(nh, nl, O::lo(x1, y1)));
+    } else if constexpr (K == 3) {
+        u16x2 mid = O::lo3(O::hi3(mh, ml, O::hi(nh, nl)), x1, y1);
+        return O::hi3(O::lo(mh, ml), O::lo(nh, nl), mid);
+    } else {
+        static_assert(K == 4, "k = 2, 3, 4");
+        u16x2 b2 = O::lo(O::hi(mh, ml), O::hi(nh, nl));
+        u16x2 c13 = O::lo3(O::hi(O::lo(mh, ml), O::lo(nh, nl)), x1, y1);
+        return O::hi3(O::lo(l0, l1), O::lo(k0, k1), O::hi(b2, c13));
+    }
 }
 
 template <int K>
 __device__ __forceinline__ u16x2 kth_largest(const u16x2 (&s)[8])
 {
     static_assert(K >= 1 && K <= 8, "k in 1..8");
-    // Each half is sorted as two pairs: A_(1) = max(h0, h1), and the middle
-    // two of A are {mh, ml} = {min(h0, h1), max(l0, l1)} (A_(2) their max,
-    // A_(3) their min); likewise B with g, k, nh, nl.
-    if constexpr (K == 3) {
-        // m_3 = max(A_(3), B_(3), min(A_(1), B_(2)), min(A_(2), B_(1))); the
-        // last two terms together equal min(max(A_(2), B_(2)), A_(1), B_(1)),
-        // and max(A_(2), B_(2)) is the largest of mh, ml, nh, nl
-        u16x2 h0 = vmax(s[0], s[1]), l0 = vmin(s[0], s[1]);
-        u16x2 h1 = vmax(s[2], s[3]), l1 = vmin(s[2], s[3]);
-        u16x2 x1 = vmax(h0, h1), mh = vmin(h0, h1), ml = vmax(l0, l1);
-        u16x2 g0 = vmax(s[4], s[5]), k0 = vmin(s[4], s[5]);
-        u16x2 g1 = vmax(s[6], s[7]), k1 = vmin(s[6], s[7]);
-        u16x2 y1 = vmax(g0, g1), nh = vmin(g0, g1), nl = vmax(k0, k1);
-        u16x2 mid = vmin3(vmax3(mh, ml, vmax(nh, nl)), x1, y1);
-        return vmax3(vmin(mh, ml), vmin(nh, nl), mid);
-    } else if constexpr (K == 2) {
-        // m_2 = max(A_(2), B_(2), min(A_(1), B_(1)))
-        u16x2 h0 = vmax(s[0], s[1]), l0 = vmin(s[0], s[1]);
-        u16x2 h1 = vmax(s[2], s[3]), l1 = vmin(s[2], s[3]);
-        u16x2 x1 = vmax(h0, h1), mh = vmin(h0, h1), ml = vmax(l0, l1);
-        u16x2 g0 = vmax(s[4], s[5]), k0 = vmin(s[4], s[5]);
-        u16x2 g1 = vmax(s[6], s[7]), k1 = vmin(s[6], s[7]);
-        u16x2 y1 = vmax(g0, g1), nh = vmin(g0, g1), nl = vmax(k0, k1);
-        return vmax3(mh, ml, vmax3(nh, nl, vmin(x1, y1)));
-    } else if constexpr (K == 1) {
+    if constexpr (K == 1)
         return vmax3(vmax3(s[0], s[1], s[2]), vmax3(s[3], s[4], s[5]), vmax(s[6], s[7]));
-    } else {
-        Sorted4 A = sort4(s[0], s[1], s[2], s[3]);
-        Sorted4 B = sort4(s[4], s[5], s[6], s[7]);
-        constexpr int lo = K > 4 ? K - 4 : 0;
-        constexpr int hi = K < 4 ? K : 4;
-        u16x2 t = vmin(A.v[lo], B.v[K - lo]);
-#pragma unroll
-        for (int i = lo + 1; i <= hi; ++i)
-            t = vmax(t, vmin(A.v[i], B.v[K - i]));
-        return t;
-    }
+    else if constexpr (K == 8)
+        return vmin3(vmin3(s[0], s[1], s[2]), vmin3(s[3], s[4], s[5]), vmin(s[6], s[7]));
+    else if constexpr (K <= 4)
+        return kth_network<K, false>(s);
+    else
+        return kth_network<9 - K, true>(s);
 }
 
 // ------------------------------------------------------------ image rows
