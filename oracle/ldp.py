@@ -19,7 +19,9 @@ the design notes of the repository):
   columns of M0, M1 and M7 coincide.
 * Eq. 1 is a correlation (no kernel flip): m_i = sum_{a,b in {-1,0,1}}
   M_i[a+1][b+1] * I[x+a][y+b].
-* Responses are signed, as Eq. 2 is written (no absolute value).
+* Responses are signed, as Eq. 2 is written (no absolute value).  The
+  magnitude option ranks |m_i| instead: the convention of the original LDP
+  descriptor that Section 2.2 builds on, offered as a variant.
 * m_k is the k-th element of the eight responses sorted in descending order,
   duplicates kept (an order statistic).
 * Eq. 3 sets bit i when m_i - m_k >= 0, so every response tied with m_k sets
@@ -134,12 +136,17 @@ def codes_from_responses(resp, k):
     return code.astype(np.uint8)
 
 
-def ldp_codes(img, k=3):
+def ldp_codes(img, k=3, magnitude=False):
     """Interior LDP code map, uint8 array of shape (H-2, W-2).
 
-    Eqs. 1-3 (Sections 2.2.1-2.2.2) applied to every interior pixel.
+    Eqs. 1-3 (Sections 2.2.1-2.2.2) applied to every interior pixel.  With
+    ``magnitude`` the responses are ranked by absolute value: Eqs. 2-3 applied
+    to |m_0|, ..., |m_7|.
     """
-    return codes_from_responses(responses_direct(img), k)
+    resp = responses_direct(img)
+    if magnitude:
+        resp = np.abs(resp)
+    return codes_from_responses(resp, k)
 
 
 def cell_of(n, cells, idx):
@@ -170,7 +177,33 @@ def ldp_histograms(codes, cells_y, cells_x):
     return hist.astype(np.uint32)
 
 
-def ldp_extract(img, k, cells_y, cells_x):
+def ldp_extract(img, k, cells_y, cells_x, magnitude=False):
     """Codes and per-cell histograms of one image (Eqs. 1-5)."""
-    codes = ldp_codes(img, k)
+    codes = ldp_codes(img, k, magnitude)
     return codes, ldp_histograms(codes, cells_y, cells_x)
+
+
+def pattern_values(k):
+    """Eq. 4's pattern values C_1, C_2, ...: the codes with exactly k bits set,
+    in ascending order (C(8, k) of them; Eq. 6 lists 56 bins for k = 3)."""
+    if not 1 <= k <= 8:
+        raise ValueError("k must be in 1..8")
+    return np.array([v for v in range(NUM_BINS) if bin(v).count("1") == k], dtype=np.int64)
+
+
+def compact_histograms(hist, k):
+    """Eq. 6's feature vector for every cell of ``hist`` (raw-code bins on the
+    last axis): H_i of Eq. 4 for each pattern value C_i of pattern_values(k),
+    followed by one bin counting the pixels whose code is no pattern value
+    (a tie with m_k sets more than k bits).  Returns uint32, last axis
+    C(8, k) + 1."""
+    h = np.asarray(hist).astype(np.int64)
+    if h.shape[-1] != NUM_BINS:
+        raise ValueError("histograms must have 256 bins on the last axis")
+    C = pattern_values(k)
+    out = np.zeros(h.shape[:-1] + (len(C) + 1,), dtype=np.int64)
+    for i, c in enumerate(C):
+        out[..., i] = h[..., c]
+    others = [v for v in range(NUM_BINS) if v not in set(C.tolist())]
+    out[..., len(C)] = h[..., others].sum(axis=-1)
+    return out.astype(np.uint32)

@@ -10,7 +10,7 @@
  *     direct 3x3 correlation (no kernel flip);
  *   - Eqs. 2-3 (Section 2.2.2): m_k is the k-th element of the eight
  *     responses sorted in descending order with duplicates kept, and bit i of
- *     the code is set when m_i - m_k >= 0;
+ *     the code is set when m_i - m_k >= 0 (optionally on |m_i|);
  *   - Eqs. 4-5 (Section 2.2.3): 256-bin histograms of the codes per cell of a
  *     floor-partitioned cells_y x cells_x grid over the interior code map.
  * Conventions: x is the row, y the column; masks M0..M7 are the Kirsch
@@ -36,11 +36,12 @@ static const int KIRSCH[8][3][3] = {
     {{-3, -3, -3}, {-3, 0, 5}, {-3, 5, 5}},     /* M7 South-East */
 };
 
-/* Returns 0 on success, -1 on invalid arguments. */
-int ldp_oracle_codes(const uint8_t *img, int32_t H, int32_t W, int64_t stride,
-                     int32_t k, uint8_t *codes)
+/* flags: bit 0 set ranks the responses by absolute value (Eqs. 2-3 applied
+ * to |m_i|).  Returns 0 on success, -1 on invalid arguments. */
+int ldp_oracle_codes_ex(const uint8_t *img, int32_t H, int32_t W, int64_t stride,
+                        int32_t k, int32_t flags, uint8_t *codes)
 {
-    if (!img || !codes || H < 3 || W < 3 || stride < W || k < 1 || k > 8)
+    if (!img || !codes || H < 3 || W < 3 || stride < W || k < 1 || k > 8 || (flags & ~1))
         return -1;
     for (int32_t x = 1; x <= H - 2; ++x) {
         for (int32_t y = 1; y <= W - 2; ++y) {
@@ -51,7 +52,7 @@ int ldp_oracle_codes(const uint8_t *img, int32_t H, int32_t W, int64_t stride,
                     for (int b = 0; b < 3; ++b)
                         acc += KIRSCH[i][a][b] *
                                (int)img[(int64_t)(x + a - 1) * stride + (y + b - 1)];
-                m[i] = acc;
+                m[i] = (flags & 1) && acc < 0 ? -acc : acc;
             }
             /* descending insertion sort of a copy, duplicates kept */
             int s[8];
@@ -74,6 +75,12 @@ int ldp_oracle_codes(const uint8_t *img, int32_t H, int32_t W, int64_t stride,
         }
     }
     return 0;
+}
+
+int ldp_oracle_codes(const uint8_t *img, int32_t H, int32_t W, int64_t stride,
+                     int32_t k, uint8_t *codes)
+{
+    return ldp_oracle_codes_ex(img, H, W, stride, k, 0, codes);
 }
 
 /* hist has cells_y * cells_x * 256 entries, [(cy * cells_x + cx) * 256 + v];

@@ -33,6 +33,10 @@ def _load():
         lib.ldp_oracle_codes.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                          ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p]
         lib.ldp_oracle_codes.restype = ctypes.c_int
+        lib.ldp_oracle_codes_ex.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                            ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                            ctypes.c_void_p]
+        lib.ldp_oracle_codes_ex.restype = ctypes.c_int
         lib.ldp_oracle_histograms.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                               ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]
         lib.ldp_oracle_histograms.restype = ctypes.c_int
@@ -40,8 +44,9 @@ def _load():
     return _lib
 
 
-def ldp_codes(img, k=3):
-    """Interior code map of a 2-D uint8 image (rows may be strided)."""
+def ldp_codes(img, k=3, magnitude=False):
+    """Interior code map of a 2-D uint8 image (rows may be strided); with
+    ``magnitude`` the responses are ranked by absolute value."""
     a = np.asarray(img)
     if a.ndim != 2 or a.dtype != np.uint8:
         raise ValueError("image must be a 2-D uint8 array")
@@ -49,7 +54,8 @@ def ldp_codes(img, k=3):
         a = np.ascontiguousarray(a)
     H, W = a.shape
     out = np.empty((max(H - 2, 0), max(W - 2, 0)), dtype=np.uint8)
-    rc = _load().ldp_oracle_codes(a.ctypes.data, H, W, a.strides[0], k, out.ctypes.data)
+    rc = _load().ldp_oracle_codes_ex(a.ctypes.data, H, W, a.strides[0], k, 1 if magnitude else 0,
+                                     out.ctypes.data)
     if rc != 0:
         raise ValueError("invalid arguments to ldp_oracle_codes")
     return out
@@ -68,6 +74,6 @@ def ldp_histograms(codes, cells_y, cells_x):
     return hist
 
 
-def ldp_extract(img, k, cells_y, cells_x):
-    codes = ldp_codes(img, k)
+def ldp_extract(img, k, cells_y, cells_x, magnitude=False):
+    codes = ldp_codes(img, k, magnitude)
     return codes, ldp_histograms(codes, cells_y, cells_x)
