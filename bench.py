@@ -31,6 +31,9 @@ VALU_PEAK_T = 256 * 4 * 16 * 2.4e9 / 1e12
 # checks these figures against the generated code.
 VALU_PER_ROW_STEP = {1: 470 / 3, 2: 626 / 3, 3: 662 / 3, 4: 722 / 3, 5: 722 / 3, 6: 662 / 3,
                      7: 626 / 3, 8: 31 / 3}
+# the same for ranking by response magnitude (flags LDP_RANK_MAGNITUDE)
+VALU_PER_ROW_STEP_MAGNITUDE = {1: 824 / 3, 2: 980 / 3, 3: 1016 / 3, 4: 1076 / 3, 5: 1076 / 3,
+                               6: 1016 / 3, 7: 980 / 3, 8: 31 / 3}
 # untimed work before the warm-up steps, so that timing starts at steady clocks
 DEVICE_WARMUP_S = 0.3
 

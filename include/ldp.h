@@ -98,6 +98,52 @@ int ldp_extract(const uint8_t *img, int32_t H, int32_t W, int64_t stride, int32_
                 int32_t cells_y, int32_t cells_x, uint8_t *codes, uint32_t *hist,
                 ldp_stream_t stream);
 
+/* ---------------------------------------------------------------- variants
+ *
+ * The _ex calls take `flags`, a bitwise OR of:
+ *   LDP_RANK_MAGNITUDE  rank the responses by absolute value: Eqs. 2-3
+ *                       applied to |m_0|, ..., |m_7| (the convention of the
+ *                       original LDP descriptor that Section 2.2 builds on;
+ *                       the paper's Eq. 2 ranks signed responses, flags 0).
+ * Any other bit set: LDP_ERR_INVALID_ARG.  Flags 0 is exactly the call
+ * without _ex.
+ */
+#define LDP_RANK_MAGNITUDE 1
+#define LDP_FLAGS_ALL 1
+
+/* ldp_codes with flags. */
+int ldp_codes_ex(const uint8_t *img, int32_t H, int32_t W, int64_t stride, int32_t k,
+                 int32_t flags, uint8_t *codes, ldp_stream_t stream);
+
+/* ldp_extract with flags. */
+int ldp_extract_ex(const uint8_t *img, int32_t H, int32_t W, int64_t stride, int32_t k,
+                   int32_t flags, int32_t cells_y, int32_t cells_x, uint8_t *codes,
+                   uint32_t *hist, ldp_stream_t stream);
+
+/*
+ * Eq. 6's compact feature vector.  Eq. 4 counts the pixels whose code equals
+ * the i-th pattern value C_i; the pattern values are the C(8, k) codes with
+ * exactly k bits set (56 for k = 3), taken in ascending order.  A compact
+ * histogram is (H_1, ..., H_C(8,k)) followed by one bin that counts every
+ * other code (a tie with m_k sets more than k bits), so its bins sum to the
+ * cell's pixel count.
+ *
+ * ldp_compact_bins -- C(8, k) + 1 for k in 1..8, else LDP_ERR_INVALID_ARG.
+ *
+ * ldp_compact_histograms -- compact vectors of n_cells cells.
+ *   hist    device, n_cells * 256 uint32 (raw-code histograms, e.g. from
+ *           ldp_extract: cell c at hist[c*256]).
+ *   n_cells >= 0 (0: nothing is launched).
+ *   k       1..8, the k the codes were made with.
+ *   out     device, n_cells * ldp_compact_bins(k) uint32, cell c at
+ *           out[c * ldp_compact_bins(k)], overwritten; must not overlap hist.
+ * Errors: LDP_ERR_INVALID_ARG for k outside 1..8, n_cells < 0 or a null
+ * pointer with n_cells > 0.
+ */
+int32_t ldp_compact_bins(int32_t k);
+int ldp_compact_histograms(const uint32_t *hist, int64_t n_cells, int32_t k, uint32_t *out,
+                           ldp_stream_t stream);
+
 /* ---------------------------------------------------------------- batches
  *
  * Many images of any sizes in ONE persistent launch: the work (row bands of
@@ -145,6 +191,12 @@ typedef struct ldp_batch_plan ldp_batch_plan;
  */
 int ldp_batch_plan_create(ldp_batch_plan **plan, int32_t max_images, int64_t max_pixels,
                           int32_t k, int32_t cells_y, int32_t cells_x, const ldp_tune *tune);
+
+/* ldp_batch_plan_create with flags (LDP_RANK_MAGNITUDE); the plan's runs give
+ * each image ldp_extract_ex's results with these flags. */
+int ldp_batch_plan_create_ex(ldp_batch_plan **plan, int32_t max_images, int64_t max_pixels,
+                             int32_t k, int32_t flags, int32_t cells_y, int32_t cells_x,
+                             const ldp_tune *tune);
 
 /*
  * ldp_batch_plan_set -- (re)load the batch: `descs` is a HOST array of n

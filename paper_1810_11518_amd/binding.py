@@ -20,10 +20,14 @@ LDP_ERR_NO_MEMORY = -3
 LDP_ERR_UNSUPPORTED = -4
 LDP_ERR_BUSY = -5
 
+# flags of the _ex calls
+LDP_RANK_MAGNITUDE = 1
+
 # every symbol include/ldp.h declares
 EXPORTED = [
     "ldp_status_string", "ldp_version", "ldp_codes", "ldp_histograms", "ldp_extract",
-    "ldp_batch_plan_create", "ldp_batch_plan_set", "ldp_batch_run", "ldp_batch_run_per_image",
+    "ldp_codes_ex", "ldp_extract_ex", "ldp_compact_bins", "ldp_compact_histograms",
+    "ldp_batch_plan_create", "ldp_batch_plan_create_ex", "ldp_batch_plan_set", "ldp_batch_run", "ldp_batch_run_per_image",
     "ldp_batch_plan_info", "ldp_batch_plan_destroy",
     "ldp_now", "ldp_server_create", "ldp_server_submit", "ldp_server_poll",
     "ldp_server_stats_get", "ldp_server_destroy",
@@ -112,8 +116,14 @@ def load():
         "ldp_codes": (ctypes.c_int, [p, i32, i32, i64, i32, p, p]),
         "ldp_histograms": (ctypes.c_int, [p, i32, i32, i32, i32, p, p]),
         "ldp_extract": (ctypes.c_int, [p, i32, i32, i64, i32, i32, i32, p, p, p]),
+        "ldp_codes_ex": (ctypes.c_int, [p, i32, i32, i64, i32, i32, p, p]),
+        "ldp_extract_ex": (ctypes.c_int, [p, i32, i32, i64, i32, i32, i32, i32, p, p, p]),
+        "ldp_compact_bins": (i32, [i32]),
+        "ldp_compact_histograms": (ctypes.c_int, [p, i64, i32, p, p]),
         "ldp_batch_plan_create": (ctypes.c_int, [ctypes.POINTER(p), i32, i64, i32, i32, i32,
                                                  ctypes.POINTER(Tune)]),
+        "ldp_batch_plan_create_ex": (ctypes.c_int, [ctypes.POINTER(p), i32, i64, i32, i32, i32,
+                                                    i32, ctypes.POINTER(Tune)]),
         "ldp_batch_plan_set": (ctypes.c_int, [p, ctypes.POINTER(ImageDesc), i32, p]),
         "ldp_batch_run": (ctypes.c_int, [p, p]),
         "ldp_batch_run_per_image": (ctypes.c_int, [p, p]),
@@ -167,13 +177,15 @@ def _image_args(img):
     return img.data_ptr(), int(H), int(W), int(img.stride(0))
 
 
-def codes(img, k=3, out=None, stream=None):
-    """LDP codes of every interior pixel: uint8 tensor (H-2, W-2)."""
+def codes(img, k=3, out=None, stream=None, flags=0):
+    """LDP codes of every interior pixel: uint8 tensor (H-2, W-2).  ``flags``:
+    LDP_RANK_MAGNITUDE ranks |m_i|."""
     import torch
     ptr, H, W, stride = _image_args(img)
     if out is None:
         out = torch.empty((max(H - 2, 0), max(W - 2, 0)), dtype=torch.uint8, device=img.device)
-    _check(load().ldp_codes(ptr, H, W, stride, k, out.data_ptr(), _stream(stream)), "ldp_codes")
+    _check(load().ldp_codes_ex(ptr, H, W, stride, k, flags, out.data_ptr(), _stream(stream)),
+           "ldp_codes_ex")
     return out
 
 
@@ -192,7 +204,7 @@ def histograms(code_map, cells_y, cells_x, out=None, stream=None):
 
 
 def extract(img, k, cells_y, cells_x, want_codes=True, codes_out=None, hist_out=None,
-            stream=None):
+            stream=None, flags=0):
     """Codes and per-cell histograms in one launch: (codes or None, hist)."""
     import torch
     ptr, H, W, stride = _image_args(img)
@@ -201,23 +213,47 @@ def extract(img, k, cells_y, cells_x, want_codes=True, codes_out=None, hist_out=
     if hist_out is None:
         hist_out = torch.empty((cells_y, cells_x, 256), dtype=torch.int32, device=img.device)
     cptr = codes_out.data_ptr() if want_codes else None
-    _check(load().ldp_extract(ptr, H, W, stride, k, cells_y, cells_x, cptr,
-                              hist_out.data_ptr(), _stream(stream)), "ldp_extract")
+    _check(load().ldp_extract_ex(ptr, H, W, stride, k, flags, cells_y, cells_x, cptr,
+                                 hist_out.data_ptr(), _stream(stream)), "ldp_extract_ex")
     return (codes_out if want_codes else None), hist_out
+
+
+def compact_bins(k):
+    """C(8, k) + 1: bins of Eq. 6's compact vector plus the tie bin."""
+    n = load().ldp_compact_bins(k)
+    if n < 0:
+        raise LdpError(n, "ldp_compact_bins")
+    return int(n)
+
+
+def compact_histograms(hist, k, out=None, stream=None):
+    """Compact vectors of raw-code histograms (last axis 256, contiguous
+    int32/uint32 device tensor): same leading shape, last axis
+    compact_bins(k)."""
+    import torch
+    if hist.dtype != torch.int32 or hist.shape[-1] != 256 or not hist.is_contiguous():
+        raise ValueError("histograms must be a contiguous int32 tensor with 256 bins last")
+    n_cells = hist.numel() // 256
+    nb = compact_bins(k)
+    if out is None:
+        out = torch.empty(tuple(hist.shape[:-1]) + (nb,), dtype=torch.int32, device=hist.device)
+    _check(load().ldp_compact_histograms(hist.data_ptr(), n_cells, k, out.data_ptr(),
+                                         _stream(stream)), "ldp_compact_histograms")
+    return out
 
 
 class BatchPlan:
     """A persistent, graph-captured launch over many images (ldp_batch_*)."""
 
-    def __init__(self, max_images, max_pixels, k, cells_y, cells_x, tune=None):
+    def __init__(self, max_images, max_pixels, k, cells_y, cells_x, tune=None, flags=0):
         self._lib = load()
         self._plan = ctypes.c_void_p()
         t = make_tune(tune) if tune is not None else None
-        _check(self._lib.ldp_batch_plan_create(ctypes.byref(self._plan), max_images, max_pixels,
-                                               k, cells_y, cells_x,
-                                               ctypes.byref(t) if t is not None else None),
-               "ldp_batch_plan_create")
-        self.k, self.cells = k, (cells_y, cells_x)
+        _check(self._lib.ldp_batch_plan_create_ex(ctypes.byref(self._plan), max_images,
+                                                  max_pixels, k, flags, cells_y, cells_x,
+                                                  ctypes.byref(t) if t is not None else None),
+               "ldp_batch_plan_create_ex")
+        self.k, self.cells, self.flags = k, (cells_y, cells_x), flags
 
     @staticmethod
     def descs(imgs, codes, hists, strides=None, Hs=None, Ws=None):

@@ -32,7 +32,7 @@ __global__ void clear_counter_kernel(uint32_t *meta) { meta[1] = 0; }
 #define LDP_BATCH_ATTR
 #endif
 
-template <int K>
+template <int K, int MODE>
 __global__ void __launch_bounds__(1024) LDP_BATCH_ATTR batch_kernel(const ldp_image_desc *__restrict__ descs,
                                                      const Item *__restrict__ items,
                                                      uint32_t *meta, int32_t cells_y,
@@ -55,32 +55,39 @@ __global__ void __launch_bounds__(1024) LDP_BATCH_ATTR batch_kernel(const ldp_im
         const int32_t r0 = cell_start(w.cy0, im.Hc, cells_y);
         const int32_t r1 = cell_start(w.cy1, im.Hc, cells_y);
         // a null code pointer gives an empty store range: stores are dropped
-        fused_item<K, true>(im, lds, cells_y, cells_x, w.cy0, w.cy1, r0, r1, d.hist, false,
+        fused_item<K, MODE, true>(im, lds, cells_y, cells_x, w.cy0, w.cy1, r0, r1, d.hist, false,
                             w.min_rows);
     }
 }
 
 typedef void (*batch_fn)(const ldp_image_desc *, const Item *, uint32_t *, int32_t, int32_t);
 
-static batch_fn batch_kernel_for(int k)
+template <int MODE>
+static batch_fn batch_kernel_for_mode(int k)
 {
     switch (k) {
-    case 1: return batch_kernel<1>;
-    case 2: return batch_kernel<2>;
-    case 3: return batch_kernel<3>;
-    case 4: return batch_kernel<4>;
-    case 5: return batch_kernel<5>;
-    case 6: return batch_kernel<6>;
-    case 7: return batch_kernel<7>;
-    case 8: return batch_kernel<8>;
+    case 1: return batch_kernel<1, MODE>;
+    case 2: return batch_kernel<2, MODE>;
+    case 3: return batch_kernel<3, MODE>;
+    case 4: return batch_kernel<4, MODE>;
+    case 5: return batch_kernel<5, MODE>;
+    case 6: return batch_kernel<6, MODE>;
+    case 7: return batch_kernel<7, MODE>;
+    case 8: return batch_kernel<8, MODE>;
     }
     return nullptr;
+}
+
+static batch_fn batch_kernel_for(int k, int mode)
+{
+    return mode == RANK_MAGNITUDE ? batch_kernel_for_mode<RANK_MAGNITUDE>(k)
+                                  : batch_kernel_for_mode<RANK_SIGNED>(k);
 }
 
 }  // namespace ldp
 
 struct ldp_batch_plan {
-    int32_t k = 3, cells_y = 1, cells_x = 1, max_images = 0;
+    int32_t k = 3, flags = 0, cells_y = 1, cells_x = 1, max_images = 0;
     int64_t max_pixels = 0, max_items = 0;
     int32_t threads = 256, grid = 0;
     int32_t n_classes = 1;
@@ -124,17 +131,20 @@ void release(ldp_batch_plan *p)
 
 extern "C" {
 
-int ldp_batch_plan_create(ldp_batch_plan **out, int32_t max_images, int64_t max_pixels, int32_t k,
-                          int32_t cells_y, int32_t cells_x, const ldp_tune *tune)
+int ldp_batch_plan_create_ex(ldp_batch_plan **out, int32_t max_images, int64_t max_pixels,
+                             int32_t k, int32_t flags, int32_t cells_y, int32_t cells_x,
+                             const ldp_tune *tune)
 {
-    if (!out || max_images < 1 || max_pixels < 9 || k < 1 || k > 8 || cells_y < 1 ||
-        cells_x < 1 || cells_y > LDP_MAX_SIDE - 2 || cells_x > ldp::kMaxFusedCellsX)
+    if (!out || max_images < 1 || max_pixels < 9 || k < 1 || k > 8 || !ldp::flags_ok(flags) ||
+        cells_y < 1 || cells_x < 1 || cells_y > LDP_MAX_SIDE - 2 ||
+        cells_x > ldp::kMaxFusedCellsX)
         return LDP_ERR_INVALID_ARG;
     *out = nullptr;
     ldp_batch_plan *p = new (std::nothrow) ldp_batch_plan();
     if (!p)
         return LDP_ERR_NO_MEMORY;
     p->k = k;
+    p->flags = flags;
     p->cells_y = cells_y;
     p->cells_x = cells_x;
     p->max_images = max_images;
@@ -202,7 +212,7 @@ int ldp_batch_plan_create(ldp_batch_plan **out, int32_t max_images, int64_t max_
     if (hipMemset(p->d_meta, 0, 64) != hipSuccess)
         return fail(LDP_ERR_HIP);
 
-    ldp::batch_fn fn = ldp::batch_kernel_for(k);
+    ldp::batch_fn fn = ldp::batch_kernel_for(k, ldp::rank_mode(flags));
     if (!p->grid) {
         int per_cu = 0, cus = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(fn),
@@ -228,6 +238,12 @@ int ldp_batch_plan_create(ldp_batch_plan **out, int32_t max_images, int64_t max_
         return fail(LDP_ERR_HIP);
     *out = p;
     return LDP_OK;
+}
+
+int ldp_batch_plan_create(ldp_batch_plan **out, int32_t max_images, int64_t max_pixels, int32_t k,
+                          int32_t cells_y, int32_t cells_x, const ldp_tune *tune)
+{
+    return ldp_batch_plan_create_ex(out, max_images, max_pixels, k, 0, cells_y, cells_x, tune);
 }
 
 int ldp_batch_plan_set(ldp_batch_plan *p, const ldp_image_desc *descs, int32_t n,
@@ -308,7 +324,7 @@ int ldp_batch_run_per_image(ldp_batch_plan *p, ldp_stream_t stream)
     if (!p)
         return LDP_ERR_INVALID_ARG;
     for (const ldp_image_desc &d : p->descs) {
-        int st = ldp::launch_extract(d.img, d.H, d.W, d.stride, p->k, p->cells_y, p->cells_x,
+        int st = ldp::launch_extract(d.img, d.H, d.W, d.stride, p->k, p->flags, p->cells_y, p->cells_x,
                                      d.codes, d.hist, (hipStream_t)stream);
         if (st != LDP_OK)
             return st;

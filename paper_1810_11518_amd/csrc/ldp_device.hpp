@@ -40,6 +40,11 @@ namespace ldp {
 
 typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));
 
+// What the eight values ranked per pixel are (a template argument of every
+// kernel): the S_i, whose order is that of the signed responses m_i = 8*S_i -
+// 3*T (Eq. 2 as written), or |m_i| (ranking by response magnitude).
+enum : int { RANK_SIGNED = 0, RANK_MAGNITUDE = 1 };
+
 __device__ __forceinline__ u16x2 V(uint32_t x) { return __builtin_bit_cast(u16x2, x); }
 __device__ __forceinline__ uint32_t U(u16x2 v) { return __builtin_bit_cast(uint32_t, v); }
 __device__ __forceinline__ u16x2 vmax(u16x2 a, u16x2 b) { return __builtin_elementwise_max(a, b); }
@@ -148,6 +153,9 @@ __device__ __forceinline__ uint32_t pair_sel(int a)
     return (uint32_t)a | (0x0Cu << 8) | ((uint32_t)(4 + a) << 16) | (0x0Cu << 24);
 }
 
+// With RANK_MAGNITUDE the pairs hold 8 * byte, so every sum below is 8 times
+// the pixel sum (8 * S_i <= 6120, 8 * T <= 16320: still no carry).
+template <int MODE>
 __device__ __forceinline__ void make_row(Row &r, uint32_t u0, uint32_t u1, uint32_t u2)
 {
     r.X[0] = __builtin_amdgcn_perm(u1, u0, pair_sel(0));
@@ -156,6 +164,11 @@ __device__ __forceinline__ void make_row(Row &r, uint32_t u0, uint32_t u1, uint3
     r.X[3] = __builtin_amdgcn_perm(u1, u0, pair_sel(3));
     r.X[4] = __builtin_amdgcn_perm(u2, u1, pair_sel(0));
     r.X[5] = __builtin_amdgcn_perm(u2, u1, pair_sel(1));
+    if constexpr (MODE == RANK_MAGNITUDE) {
+#pragma unroll
+        for (int a = 0; a < 6; ++a)
+            r.X[a] <<= 3;  // fields <= 255 * 8: nothing crosses into the next field
+    }
     // two 16-bit fields per add; no field exceeds 765, so nothing carries
     uint32_t h1 = r.X[1] + r.X[2];
     uint32_t h3 = r.X[3] + r.X[4];
@@ -177,7 +190,7 @@ struct RawRow {
 // (above), m (centre) and b (below).  Vt[a] = X_t[a] + X_m[a] and
 // Vb[a] = X_m[a] + X_b[a] are the vertical pair sums.  Returns the codes of
 // pixels 0..3 in `lo` and 4..7 in `hi` (byte p = pixel p).
-template <int K>
+template <int K, int MODE>
 __device__ __forceinline__ void code_row(const Row &t, const Row &b, const uint32_t (&Vt)[6],
                                          const uint32_t (&Vb)[6], uint32_t &lo, uint32_t &hi)
 {
@@ -210,6 +223,18 @@ __device__ __forceinline__ void code_row(const Row &t, const Row &b, const uint3
                 S[e][5] = Vb[a - 1] + b.X[a];   // SW  W + SW + S
                 S[e][6] = b.R[c];               // S   row below
                 S[e][7] = Vb[a + 1] + b.X[a];   // SE  S + SE + E
+                if constexpr (MODE == RANK_MAGNITUDE) {
+                    // the sums are 8 * S_i and 8 * T (scaled rows); 3 * T is
+                    // ((8 * T) >> 3) * 3 (the low 3 bits of each field are 0,
+                    // so the shift moves nothing across fields), and
+                    // |m_i| = |8 * S_i - 3 * T| = max - min per field
+                    const uint32_t T8 = col[a + 1] + col[a - 1] + t.X[a] + b.X[a];
+                    const uint32_t T1 = T8 >> 3;
+                    const u16x2 T3 = V((T1 << 1) + T1);
+#pragma unroll
+                    for (int i = 0; i < 8; ++i)
+                        S[e][i] = U(vmax(V(S[e][i]), T3)) - U(vmin(V(S[e][i]), T3));
+                }
                 u16x2 Sv[8];
 #pragma unroll
                 for (int i = 0; i < 8; ++i)

@@ -81,12 +81,13 @@ __device__ __forceinline__ void load_raw(RawRow &rr, __amdgpu_buffer_rsrc_t rsrc
     rr.w[3] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)(a + 12), 0, 0);
 }
 
+template <int MODE>
 __device__ __forceinline__ void unpack_raw(Row &r, const RawRow &rr)
 {
     uint32_t u0 = __builtin_amdgcn_alignbyte(rr.w[1], rr.w[0], rr.s);
     uint32_t u1 = __builtin_amdgcn_alignbyte(rr.w[2], rr.w[1], rr.s);
     uint32_t u2 = __builtin_amdgcn_alignbyte(rr.w[3], rr.w[2], rr.s);
-    make_row(r, u0, u1, u2);
+    make_row<MODE>(r, u0, u1, u2);
 }
 
 // Column group of a lane: its first code column (groups of 8, the last one
@@ -142,19 +143,19 @@ __device__ __forceinline__ uint32_t bin_addr(uint32_t x, uint32_t d, int q, uint
 
 // One code row: the next image row arrives in `raw` and becomes `b`; t and m
 // are the two rows above; Vt = X_t + X_m.  Writes Vb = X_m + X_b.
-template <int K, bool HIST, bool CODES>
+template <int K, int MODE, bool HIST, bool CODES>
 __device__ __forceinline__ void step(const ImgView &im, uint32_t *lds_bins, Walk &w, RawRow &raw,
                                      const Row &t, const Row &m, Row &b, const uint32_t (&Vt)[6],
                                      uint32_t (&Vb)[6])
 {
-    unpack_raw(b, raw);
+    unpack_raw<MODE>(b, raw);
     w.off = min(w.off + im.stride, w.last_off);
     load_raw(raw, im.rsrc, w.off);  // prefetch the row after (clamped to the last)
 #pragma unroll
     for (int a = 0; a < 6; ++a)
         Vb[a] = m.X[a] + b.X[a];
     uint32_t lo, hi;
-    code_row<K>(t, b, Vt, Vb, lo, hi);
+    code_row<K, MODE>(t, b, Vt, Vb, lo, hi);
     if constexpr (CODES) {
         // dword stores at any byte offset (the target allows unaligned access)
         __builtin_amdgcn_raw_buffer_store_b32(lo, im.crsrc, (int)w.coff, 0, 0);
@@ -179,7 +180,7 @@ __device__ __forceinline__ void step(const ImgView &im, uint32_t *lds_bins, Walk
 
 // Run code rows [r0, r1) of the column group `c`; with HIST they all lie in
 // the cell row whose histograms start at LDS byte `rowb`.
-template <int K, bool HIST, bool CODES>
+template <int K, int MODE, bool HIST, bool CODES>
 __device__ __forceinline__ void run_task(const ImgView &im, uint32_t *lds_bins, uint32_t rowb,
                                          const Cols &c, int32_t r0, int32_t r1)
 {
@@ -195,10 +196,10 @@ __device__ __forceinline__ void run_task(const ImgView &im, uint32_t *lds_bins, 
     Row A, B, C;
     uint32_t VAB[6], VBC[6], VCA[6];
     load_raw(raw, im.rsrc, w.off);
-    unpack_raw(A, raw);
+    unpack_raw<MODE>(A, raw);
     w.off += im.stride;
     load_raw(raw, im.rsrc, w.off);
-    unpack_raw(B, raw);
+    unpack_raw<MODE>(B, raw);
     w.off += im.stride;
     load_raw(raw, im.rsrc, w.off);
 #pragma unroll
@@ -209,7 +210,7 @@ __device__ __forceinline__ void run_task(const ImgView &im, uint32_t *lds_bins, 
     int32_t n = r1 - r0;
 #ifdef LDP_ROLLED_ROWS
     for (; n > 0; --n) {
-        step<K, HIST, CODES>(im, lds_bins, w, raw, A, B, C, VAB, VBC);
+        step<K, MODE, HIST, CODES>(im, lds_bins, w, raw, A, B, C, VAB, VBC);
         A = B;
         B = C;
 #pragma unroll
@@ -219,20 +220,20 @@ __device__ __forceinline__ void run_task(const ImgView &im, uint32_t *lds_bins, 
     (void)VCA;
 #else
     for (; n >= 3; n -= 3) {
-        step<K, HIST, CODES>(im, lds_bins, w, raw, A, B, C, VAB, VBC);
-        step<K, HIST, CODES>(im, lds_bins, w, raw, B, C, A, VBC, VCA);
-        step<K, HIST, CODES>(im, lds_bins, w, raw, C, A, B, VCA, VAB);
+        step<K, MODE, HIST, CODES>(im, lds_bins, w, raw, A, B, C, VAB, VBC);
+        step<K, MODE, HIST, CODES>(im, lds_bins, w, raw, B, C, A, VBC, VCA);
+        step<K, MODE, HIST, CODES>(im, lds_bins, w, raw, C, A, B, VCA, VAB);
     }
     if (n >= 1)
-        step<K, HIST, CODES>(im, lds_bins, w, raw, A, B, C, VAB, VBC);
+        step<K, MODE, HIST, CODES>(im, lds_bins, w, raw, A, B, C, VAB, VBC);
     if (n >= 2)
-        step<K, HIST, CODES>(im, lds_bins, w, raw, B, C, A, VBC, VCA);
+        step<K, MODE, HIST, CODES>(im, lds_bins, w, raw, B, C, A, VBC, VCA);
 #endif
 }
 
 // Code rows [r0, r1) of a code map narrower than 8 columns: one lane, the
 // pixels past the map masked (counted in the discard cell).
-template <int K, bool HIST, bool CODES>
+template <int K, int MODE, bool HIST, bool CODES>
 __device__ void run_task_narrow(const ImgView &im, uint32_t *lds_bins, uint32_t rowb,
                                 int32_t cells_x, int32_t r0, int32_t r1)
 {
@@ -241,9 +242,9 @@ __device__ void run_task_narrow(const ImgView &im, uint32_t *lds_bins, uint32_t 
     RawRow raw;
     Row t, m, b;
     load_raw(raw, im.rsrc, off);
-    unpack_raw(t, raw);
+    unpack_raw<MODE>(t, raw);
     load_raw(raw, im.rsrc, off + im.stride);
-    unpack_raw(m, raw);
+    unpack_raw<MODE>(m, raw);
     uint32_t Vt[6], Vb[6];
 #pragma unroll
     for (int a = 0; a < 6; ++a)
@@ -258,12 +259,12 @@ __device__ void run_task_narrow(const ImgView &im, uint32_t *lds_bins, uint32_t 
     }
     for (int32_t r = r0; r < r1; ++r) {
         load_raw(raw, im.rsrc, off + (uint32_t)(r + 2 - r0) * im.stride);
-        unpack_raw(b, raw);
+        unpack_raw<MODE>(b, raw);
 #pragma unroll
         for (int a = 0; a < 6; ++a)
             Vb[a] = m.X[a] + b.X[a];
         uint32_t lo, hi;
-        code_row<K>(t, b, Vt, Vb, lo, hi);
+        code_row<K, MODE>(t, b, Vt, Vb, lo, hi);
         if constexpr (CODES) {
             const uint32_t coff = (uint32_t)r * (uint32_t)im.Wc;
             for (int p = 0; p < nvalid; ++p)
@@ -298,7 +299,7 @@ __device__ void run_task_narrow(const ImgView &im, uint32_t *lds_bins, uint32_t 
 // [0, base) take the q-band groups, column group fastest (neighbouring lanes
 // read neighbouring columns), lanes [base, threads) the (q+1)-band groups.
 // Wider maps (more column groups than threads) take whole cell rows per task.
-template <int K, bool CODES>
+template <int K, int MODE, bool CODES>
 __device__ __forceinline__ void fused_item(const ImgView &im, uint32_t *lds, int32_t cells_y,
                                            int32_t cells_x, int32_t cy0, int32_t cy1, int32_t r0,
                                            int32_t r1, uint32_t *hist, bool atomic_flush,
@@ -324,7 +325,7 @@ __device__ __forceinline__ void fused_item(const ImgView &im, uint32_t *lds, int
                 const int32_t a0 = a + (int32_t)(((uint32_t)nr * tid) / (uint32_t)nsub);
                 const int32_t a1 = a + (int32_t)(((uint32_t)nr * (tid + 1)) / (uint32_t)nsub);
                 if (a1 > a0)
-                    run_task_narrow<K, true, CODES>(im, lds, (cy - cy0) * row_bytes, cells_x,
+                    run_task_narrow<K, MODE, true, CODES>(im, lds, (cy - cy0) * row_bytes, cells_x,
                                                     a0, a1);
             }
         }
@@ -359,7 +360,7 @@ __device__ __forceinline__ void fused_item(const ImgView &im, uint32_t *lds, int
                     const int32_t a0 = a + (int32_t)((nr * sb) / nb);
                     const int32_t a1 = a + (int32_t)((nr * (sb + 1)) / nb);
                     if (a1 > a0)
-                        run_task<K, true, CODES>(im, lds, (cy - cy0) * row_bytes, c, a0, a1);
+                        run_task<K, MODE, true, CODES>(im, lds, (cy - cy0) * row_bytes, c, a0, a1);
                 }
             }
         } else {
@@ -369,7 +370,7 @@ __device__ __forceinline__ void fused_item(const ImgView &im, uint32_t *lds, int
                     b = min(r1, cell_start(cy + 1, im.Hc, cells_y));
                 }
                 for (int32_t g = tid; g < ngroups; g += nthreads)
-                    run_task<K, true, CODES>(im, lds, (cy - cy0) * row_bytes,
+                    run_task<K, MODE, true, CODES>(im, lds, (cy - cy0) * row_bytes,
                                              group_cols<true>(im, cells_x, g), a, b);
             }
         }

@@ -29,16 +29,21 @@ inline int check_cells(int32_t H, int32_t W, int32_t cells_y, int32_t cells_x)
     return LDP_OK;
 }
 
+inline bool flags_ok(int32_t flags) { return (flags & ~LDP_FLAGS_ALL) == 0; }
+
+// Ranking mode of the kernels (ldp_device.hpp) for the public flags.
+inline int rank_mode(int32_t flags) { return (flags & LDP_RANK_MAGNITUDE) ? 1 : 0; }
+
 // Largest cells_x the fused kernels keep in LDS (one cell row, 1 KiB per
 // cell, plus a discard cell).
 constexpr int32_t kMaxFusedCellsX = 63;
 
 int launch_codes(const uint8_t *img, int32_t H, int32_t W, int64_t stride, int32_t k,
-                 uint8_t *codes, hipStream_t s);
+                 int32_t flags, uint8_t *codes, hipStream_t s);
 int launch_histograms(const uint8_t *codes, int32_t H, int32_t W, int32_t cells_y,
                       int32_t cells_x, uint32_t *hist, hipStream_t s);
 int launch_extract(const uint8_t *img, int32_t H, int32_t W, int64_t stride, int32_t k,
-                   int32_t cells_y, int32_t cells_x, uint8_t *codes, uint32_t *hist,
-                   hipStream_t s);
+                   int32_t flags, int32_t cells_y, int32_t cells_x, uint8_t *codes,
+                   uint32_t *hist, hipStream_t s);
 
 }  // namespace ldp

@@ -21,7 +21,7 @@ namespace ldp {
 #define LDP_CODES_ATTR
 #endif
 
-template <int K>
+template <int K, int MODE>
 __global__ void __launch_bounds__(256) LDP_CODES_ATTR codes_kernel(const uint8_t *__restrict__ img,
                                                     int64_t stride, int32_t H, int32_t W,
                                                     uint8_t *__restrict__ codes, int32_t band_rows,
@@ -36,9 +36,9 @@ __global__ void __launch_bounds__(256) LDP_CODES_ATTR codes_kernel(const uint8_t
     const int32_t r0 = band * band_rows;
     const int32_t r1 = min(r0 + band_rows, im.Hc);
     if (im.Wc < 8)
-        run_task_narrow<K, false, true>(im, nullptr, 0, 0, r0, r1);
+        run_task_narrow<K, MODE, false, true>(im, nullptr, 0, 0, r0, r1);
     else
-        run_task<K, false, true>(im, nullptr, 0, group_cols<false>(im, 0, g), r0, r1);
+        run_task<K, MODE, false, true>(im, nullptr, 0, group_cols<false>(im, 0, g), r0, r1);
 }
 
 // ---------------------------------------------------------------- histograms
@@ -84,7 +84,7 @@ __global__ void zero_kernel(uint32_t *__restrict__ p, int64_t n)
 }
 
 // ---------------------------------------------------------------- fused
-template <int K, bool CODES>
+template <int K, int MODE, bool CODES>
 __global__ void __launch_bounds__(1024) fused_kernel(const uint8_t *__restrict__ img,
                                                      int64_t stride, int32_t H, int32_t W,
                                                      uint8_t *codes, uint32_t *hist,
@@ -97,50 +97,57 @@ __global__ void __launch_bounds__(1024) fused_kernel(const uint8_t *__restrict__
     const int32_t ry0 = cell_start(cy, im.Hc, cells_y), ry1 = cell_start(cy + 1, im.Hc, cells_y);
     const int32_t r0 = ry0 + (int32_t)((int64_t)(ry1 - ry0) * sp / split);
     const int32_t r1 = ry0 + (int32_t)((int64_t)(ry1 - ry0) * (sp + 1) / split);
-    fused_item<K, CODES>(im, lds, cells_y, cells_x, cy, cy + 1, r0, r1, hist, split > 1, 4);
+    fused_item<K, MODE, CODES>(im, lds, cells_y, cells_x, cy, cy + 1, r0, r1, hist, split > 1, 4);
 }
 
 // ---------------------------------------------------------------- dispatch
-template <template <int, bool> class F, typename... Args>
-static hipError_t dispatch_k(int k, bool flag, Args &&...args)
+// F<K, MODE, FLAG>::launch(args...) for k in 1..8, the ranking mode and a flag.
+template <template <int, int, bool> class F, typename... Args>
+static hipError_t dispatch(int k, int mode, bool flag, Args &&...args)
 {
+#define LDP_CASE(KK)                                                                        \
+    case KK:                                                                                \
+        if (mode == RANK_MAGNITUDE)                                                         \
+            return flag ? F<KK, RANK_MAGNITUDE, true>::launch(args...)                      \
+                        : F<KK, RANK_MAGNITUDE, false>::launch(args...);                    \
+        return flag ? F<KK, RANK_SIGNED, true>::launch(args...)                             \
+                    : F<KK, RANK_SIGNED, false>::launch(args...);
     switch (k) {
-#define LDP_CASE(KK)                                                           \
-    case KK:                                                                   \
-        return flag ? F<KK, true>::launch(args...) : F<KK, false>::launch(args...);
         LDP_CASE(1) LDP_CASE(2) LDP_CASE(3) LDP_CASE(4)
         LDP_CASE(5) LDP_CASE(6) LDP_CASE(7) LDP_CASE(8)
-#undef LDP_CASE
     }
+#undef LDP_CASE
     return hipErrorInvalidValue;
 }
 
-template <int K, bool UNUSED>
+template <int K, int MODE, bool UNUSED>
 struct CodesLaunch {
     static hipError_t launch(dim3 grid, dim3 block, hipStream_t s, const uint8_t *img,
                              int64_t stride, int32_t H, int32_t W, uint8_t *codes, int32_t band,
                              int32_t ngroups, int32_t ntasks)
     {
-        hipLaunchKernelGGL((codes_kernel<K>), grid, block, 0, s, img, stride, H, W, codes,
+        if constexpr (UNUSED)
+            return hipErrorInvalidValue;
+        hipLaunchKernelGGL((codes_kernel<K, MODE>), grid, block, 0, s, img, stride, H, W, codes,
                            band, ngroups, ntasks);
         return hipGetLastError();
     }
 };
 
-template <int K, bool CODES>
+template <int K, int MODE, bool CODES>
 struct FusedLaunch {
     static hipError_t launch(dim3 grid, dim3 block, size_t lds, hipStream_t s, const uint8_t *img,
                              int64_t stride, int32_t H, int32_t W, uint8_t *codes,
                              uint32_t *hist, int32_t cells_y, int32_t cells_x, int32_t split)
     {
-        hipLaunchKernelGGL((fused_kernel<K, CODES>), grid, block, lds, s, img, stride, H, W, codes,
-                           hist, cells_y, cells_x, split);
+        hipLaunchKernelGGL((fused_kernel<K, MODE, CODES>), grid, block, lds, s, img, stride, H, W,
+                           codes, hist, cells_y, cells_x, split);
         return hipGetLastError();
     }
 };
 
 int launch_codes(const uint8_t *img, int32_t H, int32_t W, int64_t stride, int32_t k,
-                 uint8_t *codes, hipStream_t s)
+                 int32_t flags, uint8_t *codes, hipStream_t s)
 {
     const int32_t Hc = H - 2, Wc = W - 2;
     const int32_t ngroups = (Wc + 7) / 8;
@@ -150,8 +157,8 @@ int launch_codes(const uint8_t *img, int32_t H, int32_t W, int64_t stride, int32
     int32_t nbands = (Hc + band - 1) / band;
     int32_t ntasks = ngroups * nbands;
     dim3 block(256), grid((ntasks + 255) / 256);
-    hipError_t e = dispatch_k<CodesLaunch>(k, true, grid, block, s, img,
-                                           stride, H, W, codes, band, ngroups, ntasks);
+    hipError_t e = dispatch<CodesLaunch>(k, rank_mode(flags), false, grid, block, s, img,
+                                         stride, H, W, codes, band, ngroups, ntasks);
     return e == hipSuccess ? LDP_OK : LDP_ERR_HIP;
 }
 
@@ -180,15 +187,15 @@ int launch_histograms(const uint8_t *codes, int32_t H, int32_t W, int32_t cells_
 static size_t fused_lds_bytes(int32_t cells_x) { return hist_row_bytes(cells_x); }
 
 int launch_extract(const uint8_t *img, int32_t H, int32_t W, int64_t stride, int32_t k,
-                   int32_t cells_y, int32_t cells_x, uint8_t *codes, uint32_t *hist,
-                   hipStream_t s)
+                   int32_t flags, int32_t cells_y, int32_t cells_x, uint8_t *codes,
+                   uint32_t *hist, hipStream_t s)
 {
     const int32_t Hc = H - 2, Wc = W - 2;
     if (cells_x > kMaxFusedCellsX) {
         // one cell row of histograms does not fit in LDS: two passes
         if (!codes)
             return LDP_ERR_UNSUPPORTED;
-        int st = launch_codes(img, H, W, stride, k, codes, s);
+        int st = launch_codes(img, H, W, stride, k, flags, codes, s);
         return st != LDP_OK ? st : launch_histograms(codes, H, W, cells_y, cells_x, hist, s);
     }
     const int32_t ngroups = (Wc + 7) / 8;
@@ -204,9 +211,9 @@ int launch_extract(const uint8_t *img, int32_t H, int32_t W, int64_t stride, int
                            dim3(256), 0, s, hist, n);
     }
     size_t lds = fused_lds_bytes(cells_x);
-    hipError_t e = dispatch_k<FusedLaunch>(k, codes != nullptr,
-                                           dim3(cells_y * split), dim3(threads), lds, s, img,
-                                           stride, H, W, codes, hist, cells_y, cells_x, split);
+    hipError_t e = dispatch<FusedLaunch>(k, rank_mode(flags), codes != nullptr,
+                                         dim3(cells_y * split), dim3(threads), lds, s, img,
+                                         stride, H, W, codes, hist, cells_y, cells_x, split);
     return e == hipSuccess ? LDP_OK : LDP_ERR_HIP;
 }
 
@@ -215,15 +222,21 @@ int launch_extract(const uint8_t *img, int32_t H, int32_t W, int64_t stride, int
 // ---------------------------------------------------------------- C ABI
 extern "C" {
 
-int ldp_codes(const uint8_t *img, int32_t H, int32_t W, int64_t stride, int32_t k,
-              uint8_t *codes, ldp_stream_t stream)
+int ldp_codes_ex(const uint8_t *img, int32_t H, int32_t W, int64_t stride, int32_t k,
+                 int32_t flags, uint8_t *codes, ldp_stream_t stream)
 {
     int st = ldp::check_image(img, H, W, stride);
     if (st != LDP_OK)
         return st;
-    if (!codes || k < 1 || k > 8)
+    if (!codes || k < 1 || k > 8 || !ldp::flags_ok(flags))
         return LDP_ERR_INVALID_ARG;
-    return ldp::launch_codes(img, H, W, stride, k, codes, (hipStream_t)stream);
+    return ldp::launch_codes(img, H, W, stride, k, flags, codes, (hipStream_t)stream);
+}
+
+int ldp_codes(const uint8_t *img, int32_t H, int32_t W, int64_t stride, int32_t k,
+              uint8_t *codes, ldp_stream_t stream)
+{
+    return ldp_codes_ex(img, H, W, stride, k, 0, codes, stream);
 }
 
 int ldp_histograms(const uint8_t *codes, int32_t H, int32_t W, int32_t cells_y,
@@ -237,20 +250,27 @@ int ldp_histograms(const uint8_t *codes, int32_t H, int32_t W, int32_t cells_y,
     return ldp::launch_histograms(codes, H, W, cells_y, cells_x, hist, (hipStream_t)stream);
 }
 
-int ldp_extract(const uint8_t *img, int32_t H, int32_t W, int64_t stride, int32_t k,
-                int32_t cells_y, int32_t cells_x, uint8_t *codes, uint32_t *hist,
-                ldp_stream_t stream)
+int ldp_extract_ex(const uint8_t *img, int32_t H, int32_t W, int64_t stride, int32_t k,
+                   int32_t flags, int32_t cells_y, int32_t cells_x, uint8_t *codes,
+                   uint32_t *hist, ldp_stream_t stream)
 {
     int st = ldp::check_image(img, H, W, stride);
     if (st != LDP_OK)
         return st;
-    if (!hist || k < 1 || k > 8)
+    if (!hist || k < 1 || k > 8 || !ldp::flags_ok(flags))
         return LDP_ERR_INVALID_ARG;
     st = ldp::check_cells(H, W, cells_y, cells_x);
     if (st != LDP_OK)
         return st;
-    return ldp::launch_extract(img, H, W, stride, k, cells_y, cells_x, codes, hist,
+    return ldp::launch_extract(img, H, W, stride, k, flags, cells_y, cells_x, codes, hist,
                                (hipStream_t)stream);
+}
+
+int ldp_extract(const uint8_t *img, int32_t H, int32_t W, int64_t stride, int32_t k,
+                int32_t cells_y, int32_t cells_x, uint8_t *codes, uint32_t *hist,
+                ldp_stream_t stream)
+{
+    return ldp_extract_ex(img, H, W, stride, k, 0, cells_y, cells_x, codes, hist, stream);
 }
 
 }  // extern "C"

@@ -64,11 +64,31 @@ def test_invalid_arguments_return_before_any_launch(lib):
         t = binding.make_tune(dict(block_threads=th))
         assert lib.ldp_batch_plan_create(ctypes.byref(plan), 10, 100, 3, 7, 6, ctypes.byref(t)) == E
     assert lib.ldp_batch_run(None, None) == E
+    # variants: unknown flag bits, and the same checks as the plain calls
+    assert lib.ldp_codes_ex(p, 10, 10, 10, 3, 2, p, None) == E
+    assert lib.ldp_codes_ex(p, 10, 10, 10, 3, -1, p, None) == E
+    assert lib.ldp_codes_ex(p, 10, 10, 9, 3, binding.LDP_RANK_MAGNITUDE, p, None) == E
+    assert lib.ldp_extract_ex(p, 10, 10, 10, 3, 4, 1, 1, p, p, None) == E
+    assert lib.ldp_extract_ex(p, 10, 10, 10, 9, 1, 1, 1, p, p, None) == E
+    assert lib.ldp_batch_plan_create_ex(ctypes.byref(plan), 10, 100, 3, 8, 7, 6, None) == E
+    assert lib.ldp_compact_histograms(p, 5, 0, p, None) == E
+    assert lib.ldp_compact_histograms(p, -1, 3, p, None) == E
+    assert lib.ldp_compact_histograms(None, 5, 3, p, None) == E
+    assert lib.ldp_compact_histograms(None, 0, 3, None, None) == binding.LDP_OK  # nothing to do
     srv = ctypes.c_void_p()
     bad = binding.ServerConfig(0, 1, 1, 1, 3, 7, 6, 1, 0)
     assert lib.ldp_server_create(ctypes.byref(srv), ctypes.byref(bad)) == E
     bad = binding.ServerConfig(1 << 20, 1, 1, 9, 3, 7, 6, 1, 0)
     assert lib.ldp_server_create(ctypes.byref(srv), ctypes.byref(bad)) == E
+
+
+def test_compact_bin_counts(lib):
+    import math
+    assert lib.ldp_compact_bins(3) == 57  # Eq. 6: 56 pattern values, plus the tie bin
+    for k in range(1, 9):
+        assert lib.ldp_compact_bins(k) == math.comb(8, k) + 1
+    assert lib.ldp_compact_bins(0) == binding.LDP_ERR_INVALID_ARG
+    assert lib.ldp_compact_bins(9) == binding.LDP_ERR_INVALID_ARG
 
 
 def test_tune_struct_layout():

@@ -34,10 +34,10 @@ def _blocks(body):
     return out
 
 
-def main_loop_valu(asm, k):
-    """VALU instructions of the first innermost loop of batch_kernel<k> that
-    holds 24 LDS instructions (the x3-unrolled row loop: 8 per row step)."""
-    name = "_ZN3ldp12batch_kernelILi%dEEEvPK14ldp_image_descPKNS_4ItemEPjii" % k
+def main_loop_valu(asm, k, mode):
+    """VALU instructions of the first innermost loop of batch_kernel<k, mode>
+    that holds 24 LDS instructions (the x3-unrolled row loop: 8 per row step)."""
+    name = "_ZN3ldp12batch_kernelILi%dELi%dEEEvPK14ldp_image_descPKNS_4ItemEPjii" % (k, mode)
     i = asm.index(name + ":")
     body = asm[i:asm.index(".Lfunc_end", i)]
     blocks = _blocks(body)
@@ -60,6 +60,7 @@ def test_valu_per_row_step_matches_generated_code(tmp_path):
     p = subprocess.run(cmd, capture_output=True, text=True)
     assert p.returncode == 0, p.stderr[-2000:]
     asm = open(out).read()
-    for k in range(1, 9):
-        n = main_loop_valu(asm, k)
-        assert bench.VALU_PER_ROW_STEP[k] * 3 == pytest.approx(n), (k, n)
+    for mode, table in ((0, bench.VALU_PER_ROW_STEP), (1, bench.VALU_PER_ROW_STEP_MAGNITUDE)):
+        for k in range(1, 9):
+            n = main_loop_valu(asm, k, mode)
+            assert table[k] * 3 == pytest.approx(n), (mode, k, n)
