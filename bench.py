@@ -65,6 +65,9 @@ def parse():
     ap.add_argument("--autotune", type=float, default=0.0, metavar="SECONDS",
                     help="tune the batch plan on this batch for about SECONDS and cache it")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"))
+    ap.add_argument("--variant-steps", type=int, default=20,
+                    help="timed launches of each variant path (magnitude ranking, Eq. 6 compact "
+                         "histograms) on the same batch; 0 skips them")
     ap.add_argument("--serve-rates", default="2000,10000",
                     help="comma-separated Poisson arrival rates (images/s) for the serving "
                          "run; empty to skip")
@@ -86,6 +89,106 @@ def algorithmic_bytes(Hs, Ws, cells):
     H = Hs.astype(np.int64)
     W = Ws.astype(np.int64)
     return int((H * W + (H - 2) * (W - 2)).sum() + len(H) * cells[0] * cells[1] * 1024)
+
+
+def _timed(torch, fn, steps, warmup=3):
+    """Mean ms per call of fn over `steps` calls, HIP events on the current stream."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def variant_bench(binding, torch, args, plan_args, descs, hist, codes, code_off, Hs, Ws,
+                  ms_signed, sample, saved):
+    """The variant paths on the headline batch: Eq. 6 compact vectors of its
+    histograms (HBM-bound) and the whole batch ranked by response magnitude
+    (VALU-bound).  Outputs of the sample images go to `saved` for the CPU
+    leg's comparison with the oracle."""
+    n, pixels, k, cells, tune = plan_args
+    out = {}
+    per = cells[0] * cells[1]
+    n_cells = n * per
+    nb = binding.compact_bins(k)
+    h2 = hist[:n_cells * 256].view(n_cells, 256)
+    comp = torch.empty((n_cells, nb), dtype=torch.int32, device=hist.device)
+    ms = _timed(torch, lambda: binding.compact_histograms(h2, k, out=comp), args.variant_steps)
+    cbytes = n_cells * (256 + nb) * 4
+    saved["compact"] = {j: comp[j * per:(j + 1) * per].cpu().numpy().view(np.uint32).copy()
+                        for j in sample}
+    out["compact_histograms"] = {
+        "what": "Eq. 6 vectors: C(8,k) pattern-value bins + tie bin per cell, from the batch's "
+                "256-bin histograms", "cells": n_cells, "bins": nb, "ms": round(ms, 4),
+        "roofline": {"bound": "hbm", "achieved": round(cbytes / (ms * 1e-3) / 1e9, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(cbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "algorithmic_bytes": cbytes}}
+    plan = binding.BatchPlan(n, pixels, k, cells[0], cells[1], tune,
+                             flags=binding.LDP_RANK_MAGNITUDE)
+    plan.set(descs)
+    ms = _timed(torch, plan.run, args.variant_steps)
+    plan.close()
+    code_pixels = int(((Hs.astype(np.int64) - 2) * (Ws.astype(np.int64) - 2)).sum())
+    lane_ops = VALU_PER_ROW_STEP_MAGNITUDE[k] / 8.0 * code_pixels
+    hist_h = hist.view(n, cells[0], cells[1], 256)
+    saved["magnitude"] = {j: (codes[int(code_off[j]):int(code_off[j + 1])].cpu().numpy(),
+                              hist_h[j].cpu().numpy().view(np.uint32).copy()) for j in sample}
+    out["magnitude"] = {
+        "what": "the same batch ranked by |m_i| (flags LDP_RANK_MAGNITUDE)",
+        "value": round(pixels / (ms * 1e-3) / 1e6, 1), "unit": "Mpixel/s", "ms": round(ms, 4),
+        "vs_signed": round(ms / ms_signed, 3),
+        "roofline": {"bound": "alu", "unit": "T VALU lane-instr/s",
+                     "achieved": round(lane_ops / (ms * 1e-3) / 1e12, 2),
+                     "peak": round(VALU_PEAK_T, 2),
+                     "frac": round(lane_ops / (ms * 1e-3) / 1e12 / VALU_PEAK_T, 4),
+                     "per_pixel": round(VALU_PER_ROW_STEP_MAGNITUDE[k] / 8.0, 2)}}
+    return out
+
+
+def cpu_leg(args, host, Hs, Ws, strides, off, k, cells, n, sample, saved):
+    """The oracle on the host: timed on a bounded sample of the batch (the
+    cpu_baseline figure), then compared with the GPU outputs kept for the
+    sample images (headline, and the variants when they ran)."""
+    from oracle import ldp as oracle_np
+    from oracle import native
+    hv = host.numpy()
+
+    def image(j):
+        H, W, s, o = int(Hs[j]), int(Ws[j]), int(strides[j]), int(off[j])
+        return hv[o:o + H * s].reshape(H, s)[:, :W]
+
+    # about 10 s of single-thread oracle work
+    ncpu = min(args.cpu_images or {"batch": 800, "uneven": 800, "large": 4}[args.workload], n)
+    t0 = time.perf_counter()
+    px = 0
+    for j in range(ncpu):
+        native.ldp_extract(image(j), k, cells[0], cells[1])
+        px += int(Hs[j]) * int(Ws[j])
+    dt = time.perf_counter() - t0
+    cpu = {"value": round(px / dt / 1e6, 3), "unit": "Mpixel/s", "cores": 1, "kind": "oracle",
+           "sample": "first %d of %d images, plain C oracle (direct masks, sort), "
+                     "single thread, %.1f s" % (ncpu, n, dt)}
+    checks = {}
+    for mode, magnitude in (("signed", False), ("magnitude", True)):
+        if mode not in saved:
+            continue
+        res = []
+        for j in sample:
+            wc, wh = native.ldp_extract(image(j), k, cells[0], cells[1], magnitude=magnitude)
+            gc, gh = saved[mode][j]
+            res.append(bool((gc.reshape(wc.shape) == wc).all() and (gh == wh).all()))
+            if mode == "signed" and "compact" in saved:
+                want = oracle_np.compact_histograms(wh, k).reshape(saved["compact"][j].shape)
+                checks.setdefault("compact", []).append(bool((saved["compact"][j] == want).all()))
+        checks[mode] = res
+    return cpu, checks
 
 
 def serve_bench(binding, synth, rates, seconds, k=3, cells=(7, 6), pool_images=256):
@@ -245,18 +348,19 @@ def main():
         torch.cuda.synchronize()
         ms_plain = ep0.elapsed_time(ep1) / args.plain_steps
 
-    # results of the timed runs are the same as one run: check a few images
-    check = []
-    if not args.no_cpu:
-        from oracle import native
-        hist_h = hist.view(n, cells[0], cells[1], 256)
-        for j in [0, n // 2, n - 1]:
-            H, W, s, o = int(Hs[j]), int(Ws[j]), int(strides[j]), int(off[j])
-            im = host.numpy()[o:o + H * s].reshape(H, s)[:, :W]
-            wc, wh = native.ldp_extract(im, k, cells[0], cells[1])
-            gc = codes[int(code_off[j]):int(code_off[j + 1])].cpu().numpy().reshape(wc.shape)
-            gh = hist_h[j].cpu().numpy().view(np.uint32)
-            check.append(bool((gc == wc).all() and (gh == wh).all()))
+    # outputs of a few images, kept for the CPU leg's comparison with the oracle
+    # (the timed runs all give the same results as one run)
+    sample = [0, n // 2, n - 1]
+    hist_h = hist.view(n, cells[0], cells[1], 256)
+    saved = {"signed": {j: (codes[int(code_off[j]):int(code_off[j + 1])].cpu().numpy(),
+                            hist_h[j].cpu().numpy().view(np.uint32).copy()) for j in sample}}
+
+    # ---- variants on the same batch (they overwrite the outputs)
+    variants = None
+    if args.variant_steps > 0:
+        variants = variant_bench(binding, torch, args, plan_args=(n, pixels, k, cells, tune),
+                                 descs=descs, hist=hist, codes=codes, code_off=code_off,
+                                 Hs=Hs, Ws=Ws, ms_signed=ms_event, sample=sample, saved=saved)
 
     abytes = algorithmic_bytes(Hs, Ws, cells)
     achieved = abytes / (ms_event * 1e-3) / 1e9
@@ -277,23 +381,12 @@ def main():
     alu_achieved = alu_lane_ops / (ms_event * 1e-3) / 1e12
     alu_issued = valu * 64 / (ms_event * 1e-3) / 1e12 if valu else None
 
-    cpu = None
+    cpu, checks = None, {}
     if not args.no_cpu:
-        from oracle import native
-        # about 10 s of single-thread oracle work
-        ncpu = args.cpu_images or {"batch": 800, "uneven": 800, "large": 4}[args.workload]
-        ncpu = min(ncpu, n)
-        hv = host.numpy()
-        t0 = time.perf_counter()
-        px = 0
-        for j in range(ncpu):
-            H, W, s, o = int(Hs[j]), int(Ws[j]), int(strides[j]), int(off[j])
-            native.ldp_extract(hv[o:o + H * s].reshape(H, s)[:, :W], k, cells[0], cells[1])
-            px += H * W
-        dt = time.perf_counter() - t0
-        cpu = {"value": round(px / dt / 1e6, 3), "unit": "Mpixel/s", "cores": 1, "kind": "oracle",
-               "sample": "first %d of %d images, plain C oracle (direct masks, sort), "
-                         "single thread, %.1f s" % (ncpu, n, dt)}
+        cpu, checks = cpu_leg(args, host, Hs, Ws, strides, off, k, cells, n, sample, saved)
+    if variants:
+        for name, key in (("compact_histograms", "compact"), ("magnitude", "magnitude")):
+            variants[name]["checked_images_bit_exact"] = checks.get(key)
 
     serve = None
     if args.serve_rates and args.serve_rates.strip():
@@ -340,8 +433,9 @@ def main():
             "frac": round(abytes / (ms_plain * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "launches": "one ldp_extract per image"},
         "batched_over_plain": round(ms_plain / ms_step, 2) if ms_plain else None,
+        "variants": variants,
         "cpu_baseline": cpu,
-        "checked_images_bit_exact": check,
+        "checked_images_bit_exact": checks.get("signed"),
         "serve": serve,
         "gen_seconds": round(gen_s, 1),
     }

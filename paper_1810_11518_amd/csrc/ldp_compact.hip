@@ -97,7 +97,8 @@ int ldp_compact_histograms(const uint32_t *hist, int64_t n_cells, int32_t k, uin
     if (n_cells == 0)
         return LDP_OK;
     const int32_t npat = ldp::compact_patterns(k);
-    const int64_t blocks = std::min<int64_t>((n_cells + 3) / 4, 8192);
+    // one cell per wave (a loop only beyond 2^20 workgroups): many loads in flight
+    const int64_t blocks = std::min<int64_t>((n_cells + 3) / 4, int64_t(1) << 20);
     hipLaunchKernelGGL(ldp::compact_kernel, dim3((unsigned)blocks), dim3(256), 0,
                        (hipStream_t)stream, hist, n_cells, k, npat, out);
     return hipGetLastError() == hipSuccess ? LDP_OK : LDP_ERR_HIP;
