@@ -207,3 +207,31 @@ def compact_histograms(hist, k):
     others = [v for v in range(NUM_BINS) if v not in set(C.tolist())]
     out[..., len(C)] = h[..., others].sum(axis=-1)
     return out.astype(np.uint32)
+
+
+def window_counts(n, w):
+    """Windows of w code rows (columns) over n: ceil(n / w), the last one
+    partial when w does not divide n."""
+    return -(-n // w)
+
+
+def window_histograms(codes, win_y, win_x):
+    """256-bin histograms per window of a code map (Section 3.2's windows):
+    non-overlapping win_y x win_x windows tiling the code map from its first
+    row and column; window (wy, wx) counts code rows wy*win_y .. and columns
+    wx*win_x .., cut at the map's edge.  Returns uint32 of shape
+    (ceil(rows / win_y), ceil(columns / win_x), 256)."""
+    c = np.asarray(codes)
+    if c.ndim != 2 or c.dtype != np.uint8:
+        raise ValueError("codes must be a 2-D uint8 array")
+    if win_y < 1 or win_x < 1:
+        raise ValueError("window sides must be >= 1")
+    hc, wc = c.shape
+    ny, nx = window_counts(hc, win_y), window_counts(wc, win_x)
+    hist = np.zeros((ny, nx, NUM_BINS), dtype=np.int64)
+    for a in range(ny):
+        for b in range(nx):
+            block = c[a * win_y:(a + 1) * win_y, b * win_x:(b + 1) * win_x]
+            hist[a, b] = np.bincount(block.ravel(), minlength=NUM_BINS)
+    return hist.astype(np.uint32)
+
