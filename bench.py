@@ -31,9 +31,14 @@ VALU_PEAK_T = 256 * 4 * 16 * 2.4e9 / 1e12
 # checks these figures against the generated code.
 VALU_PER_ROW_STEP = {1: 470 / 3, 2: 626 / 3, 3: 662 / 3, 4: 722 / 3, 5: 722 / 3, 6: 662 / 3,
                      7: 626 / 3, 8: 31 / 3}
-# the same for ranking by response magnitude (flags LDP_RANK_MAGNITUDE)
+# the same for ranking by response magnitude (flags LDP_RANK_MAGNITUDE), for
+# responses computed mask by mask (LDP_DIRECT_MASKS) and for LBP labels
+# (LDP_CODE_LBP, one kernel for every k)
 VALU_PER_ROW_STEP_MAGNITUDE = {1: 824 / 3, 2: 980 / 3, 3: 1016 / 3, 4: 1076 / 3, 5: 1076 / 3,
                                6: 1016 / 3, 7: 980 / 3, 8: 31 / 3}
+VALU_PER_ROW_STEP_DIRECT = {1: 1076 / 3, 2: 1232 / 3, 3: 1268 / 3, 4: 1328 / 3, 5: 1328 / 3,
+                            6: 1268 / 3, 7: 1232 / 3, 8: 31 / 3}
+VALU_PER_ROW_STEP_LBP = 320 / 3
 # untimed work before the warm-up steps, so that timing starts at steady clocks
 DEVICE_WARMUP_S = 0.3
 
@@ -149,6 +154,31 @@ def variant_bench(binding, torch, args, plan_args, descs, hist, codes, code_off,
                      "peak": round(VALU_PEAK_T, 2),
                      "frac": round(lane_ops / (ms * 1e-3) / 1e12 / VALU_PEAK_T, 4),
                      "per_pixel": round(VALU_PER_ROW_STEP_MAGNITUDE[k] / 8.0, 2)}}
+    abytes = algorithmic_bytes(Hs, Ws, cells)
+    for name, flag, per_step, what in (
+            ("direct_masks", binding.LDP_DIRECT_MASKS, VALU_PER_ROW_STEP_DIRECT[k],
+             "the headline codes with every response computed as its own 8-tap mask "
+             "correlation (flags LDP_DIRECT_MASKS): the unaccelerated route"),
+            ("lbp", binding.LDP_CODE_LBP, VALU_PER_ROW_STEP_LBP,
+             "LBP labels and histograms of the same batch (flags LDP_CODE_LBP)")):
+        plan = binding.BatchPlan(n, pixels, k, cells[0], cells[1], tune, flags=flag)
+        plan.set(descs)
+        ms = _timed(torch, plan.run, args.variant_steps)
+        plan.close()
+        saved[name] = {j: (codes[int(code_off[j]):int(code_off[j + 1])].cpu().numpy(),
+                           hist_h[j].cpu().numpy().view(np.uint32).copy()) for j in sample}
+        lane_ops = per_step / 8.0 * code_pixels
+        out[name] = {
+            "what": what, "value": round(pixels / (ms * 1e-3) / 1e6, 1), "unit": "Mpixel/s",
+            "ms": round(ms, 4), "vs_signed": round(ms / ms_signed, 3),
+            "roofline": {"bound": "alu", "unit": "T VALU lane-instr/s",
+                         "achieved": round(lane_ops / (ms * 1e-3) / 1e12, 2),
+                         "peak": round(VALU_PEAK_T, 2),
+                         "frac": round(lane_ops / (ms * 1e-3) / 1e12 / VALU_PEAK_T, 4),
+                         "per_pixel": round(per_step / 8.0, 2),
+                         "hbm": {"achieved": round(abytes / (ms * 1e-3) / 1e9, 1),
+                                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                 "frac": round(abytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}}
     return out
 
 
@@ -175,13 +205,19 @@ def cpu_leg(args, host, Hs, Ws, strides, off, k, cells, n, sample, saved):
     cpu = {"value": round(px / dt / 1e6, 3), "unit": "Mpixel/s", "cores": 1, "kind": "oracle",
            "sample": "first %d of %d images, plain C oracle (direct masks, sort), "
                      "single thread, %.1f s" % (ncpu, n, dt)}
+    from oracle import lbp as oracle_lbp
     checks = {}
-    for mode, magnitude in (("signed", False), ("magnitude", True)):
+    for mode in ("signed", "magnitude", "direct_masks", "lbp"):
         if mode not in saved:
             continue
         res = []
         for j in sample:
-            wc, wh = native.ldp_extract(image(j), k, cells[0], cells[1], magnitude=magnitude)
+            if mode == "lbp":
+                wc = oracle_lbp.lbp_codes(image(j))
+                wh = oracle_np.ldp_histograms(wc, cells[0], cells[1])
+            else:
+                wc, wh = native.ldp_extract(image(j), k, cells[0], cells[1],
+                                            magnitude=(mode == "magnitude"))
             gc, gh = saved[mode][j]
             res.append(bool((gc.reshape(wc.shape) == wc).all() and (gh == wh).all()))
             if mode == "signed" and "compact" in saved:
@@ -385,7 +421,8 @@ def main():
     if not args.no_cpu:
         cpu, checks = cpu_leg(args, host, Hs, Ws, strides, off, k, cells, n, sample, saved)
     if variants:
-        for name, key in (("compact_histograms", "compact"), ("magnitude", "magnitude")):
+        for name, key in (("compact_histograms", "compact"), ("magnitude", "magnitude"),
+                          ("direct_masks", "direct_masks"), ("lbp", "lbp")):
             variants[name]["checked_images_bit_exact"] = checks.get(key)
 
     serve = None

@@ -100,16 +100,27 @@ int ldp_extract(const uint8_t *img, int32_t H, int32_t W, int64_t stride, int32_
 
 /* ---------------------------------------------------------------- variants
  *
- * The _ex calls take `flags`, a bitwise OR of:
+ * The _ex calls take `flags`: 0 or exactly one of
  *   LDP_RANK_MAGNITUDE  rank the responses by absolute value: Eqs. 2-3
  *                       applied to |m_0|, ..., |m_7| (the convention of the
  *                       original LDP descriptor that Section 2.2 builds on;
  *                       the paper's Eq. 2 ranks signed responses, flags 0).
- * Any other bit set: LDP_ERR_INVALID_ARG.  Flags 0 is exactly the call
- * without _ex.
+ *   LDP_DIRECT_MASKS    the codes of flags 0, with every response computed
+ *                       as Eq. 1's 8-tap mask correlation (multiply-adds, no
+ *                       shared sums): the unaccelerated LDP computation that
+ *                       Section 2.3's scheme is measured against.
+ *   LDP_CODE_LBP        Local Binary Pattern labels (Section 2.1) instead of
+ *                       LDP codes: bit i is set when the neighbour in compass
+ *                       direction i (E, NE, N, NW, W, SW, S, SE) is >= the
+ *                       centre pixel; same code map and histogram layout; k
+ *                       must be valid (1..8) and is ignored.
+ * Anything else: LDP_ERR_INVALID_ARG.  Flags 0 is exactly the call without
+ * _ex.
  */
 #define LDP_RANK_MAGNITUDE 1
-#define LDP_FLAGS_ALL 1
+#define LDP_DIRECT_MASKS 2
+#define LDP_CODE_LBP 4
+#define LDP_FLAGS_ALL 7
 
 /* ldp_codes with flags. */
 int ldp_codes_ex(const uint8_t *img, int32_t H, int32_t W, int64_t stride, int32_t k,
@@ -192,8 +203,8 @@ typedef struct ldp_batch_plan ldp_batch_plan;
 int ldp_batch_plan_create(ldp_batch_plan **plan, int32_t max_images, int64_t max_pixels,
                           int32_t k, int32_t cells_y, int32_t cells_x, const ldp_tune *tune);
 
-/* ldp_batch_plan_create with flags (LDP_RANK_MAGNITUDE); the plan's runs give
- * each image ldp_extract_ex's results with these flags. */
+/* ldp_batch_plan_create with flags (as for ldp_extract_ex); the plan's runs
+ * give each image ldp_extract_ex's results with these flags. */
 int ldp_batch_plan_create_ex(ldp_batch_plan **plan, int32_t max_images, int64_t max_pixels,
                              int32_t k, int32_t flags, int32_t cells_y, int32_t cells_x,
                              const ldp_tune *tune);

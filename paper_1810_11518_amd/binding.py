@@ -20,8 +20,10 @@ LDP_ERR_NO_MEMORY = -3
 LDP_ERR_UNSUPPORTED = -4
 LDP_ERR_BUSY = -5
 
-# flags of the _ex calls
+# flags of the _ex calls (at most one)
 LDP_RANK_MAGNITUDE = 1
+LDP_DIRECT_MASKS = 2
+LDP_CODE_LBP = 4
 
 # every symbol include/ldp.h declares
 EXPORTED = [

@@ -80,8 +80,12 @@ static batch_fn batch_kernel_for_mode(int k)
 
 static batch_fn batch_kernel_for(int k, int mode)
 {
-    return mode == RANK_MAGNITUDE ? batch_kernel_for_mode<RANK_MAGNITUDE>(k)
-                                  : batch_kernel_for_mode<RANK_SIGNED>(k);
+    switch (mode) {
+    case RANK_MAGNITUDE: return batch_kernel_for_mode<RANK_MAGNITUDE>(k);
+    case DIRECT_MASKS: return batch_kernel_for_mode<DIRECT_MASKS>(k);
+    case CODE_LBP: return batch_kernel<1, CODE_LBP>;  // LBP codes do not depend on k
+    }
+    return batch_kernel_for_mode<RANK_SIGNED>(k);
 }
 
 }  // namespace ldp

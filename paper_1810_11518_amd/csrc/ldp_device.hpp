@@ -40,10 +40,12 @@ namespace ldp {
 
 typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));
 
-// What the eight values ranked per pixel are (a template argument of every
-// kernel): the S_i, whose order is that of the signed responses m_i = 8*S_i -
-// 3*T (Eq. 2 as written), or |m_i| (ranking by response magnitude).
-enum : int { RANK_SIGNED = 0, RANK_MAGNITUDE = 1 };
+// What a pixel's code is made from (a template argument of every kernel):
+// the S_i, whose order is that of the signed responses m_i = 8*S_i - 3*T
+// (Eq. 2 as written); |m_i| (ranking by response magnitude); the signed
+// responses computed mask by mask (the unaccelerated route, same codes); or
+// the LBP comparison with the centre pixel (pair_values below).
+enum : int { RANK_SIGNED = 0, RANK_MAGNITUDE = 1, DIRECT_MASKS = 2, CODE_LBP = 3 };
 
 __device__ __forceinline__ u16x2 V(uint32_t x) { return __builtin_bit_cast(u16x2, x); }
 __device__ __forceinline__ uint32_t U(u16x2 v) { return __builtin_bit_cast(uint32_t, v); }
@@ -185,16 +187,114 @@ struct RawRow {
     uint32_t s;
 };
 
+// ------------------------------------------------------------ mask taps
+// One tap of a direct mask correlation on two 16-bit fields: acc + w * x per
+// field (modulo 2^16, exact here), w = +5 or -3 as an inline constant for both
+// fields.  Written as instructions so that the compiler cannot merge the taps
+// of different masks into shared sums: the direct route must do all 8 per
+// response.
+__device__ __forceinline__ uint32_t mad_w5(uint32_t x, uint32_t acc)
+{
+    uint32_t r;
+    asm("v_pk_mad_u16 %0, %1, 5, %2 op_sel_hi:[1,0,1]" : "=v"(r) : "v"(x), "v"(acc));
+    return r;
+}
+__device__ __forceinline__ uint32_t mad_wm3(uint32_t x, uint32_t acc)
+{
+    uint32_t r;
+    asm("v_pk_mad_u16 %0, %1, -3, %2 op_sel_hi:[1,0,1]" : "=v"(r) : "v"(x), "v"(acc));
+    return r;
+}
+
 // ------------------------------------------------------------ one code row
+// The eight values a pixel pair compares and the threshold they are compared
+// with, per mode:
+//   RANK_SIGNED     S_i (the order of m_i = 8*S_i - 3*T), threshold the k-th
+//                   largest S (Eqs. 2-3);
+//   RANK_MAGNITUDE  |m_i| = |8*S_i - 3*T|, threshold the k-th largest;
+//   DIRECT_MASKS    m_i + 3825 computed mask by mask as Eq. 1's 8-tap
+//                   correlation (weights +5 and -3, one multiply-add per tap,
+//                   no shared sums: the unaccelerated computation), threshold
+//                   the k-th largest -- the same codes as RANK_SIGNED;
+//   CODE_LBP        the eight neighbours, threshold the centre (Section 2.1).
+// Every value is below 0x8000 - threshold + 0x8000, so bit 15 of each field
+// of value + (0x8000 - threshold) is set exactly when value >= threshold.
+template <int K, int MODE>
+__device__ __forceinline__ void pair_values(const Row &t, const Row &m, const Row &b,
+                                            const uint32_t (&Vt)[6], const uint32_t (&Vb)[6],
+                                            const uint32_t (&col)[6], int c, uint32_t (&S)[8],
+                                            uint32_t &bias)
+{
+    const int a = c + 1;  // the pair's centre column pair
+    if constexpr (MODE == CODE_LBP) {
+        S[0] = m.X[a + 1];  // E
+        S[1] = t.X[a + 1];  // NE
+        S[2] = t.X[a];      // N
+        S[3] = t.X[a - 1];  // NW
+        S[4] = m.X[a - 1];  // W
+        S[5] = b.X[a - 1];  // SW
+        S[6] = b.X[a];      // S
+        S[7] = b.X[a + 1];  // SE
+        bias = 0x80008000u - m.X[a];
+        return;
+    } else {
+        if constexpr (MODE == DIRECT_MASKS) {
+            // neighbours in ring order E, NE, N, NW, W, SW, S, SE; mask i
+            // weighs neighbours i-1, i, i+1 with +5 and the rest with -3
+            const uint32_t P[8] = {m.X[a + 1], t.X[a + 1], t.X[a],     t.X[a - 1],
+                                   m.X[a - 1], b.X[a - 1], b.X[a],     b.X[a + 1]};
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                uint32_t acc = 0x0EF10EF1u;  // 3825 per field: m_i + 3825 stays in 0..7650
+                // taps from neighbour i round the ring: no two masks share a
+                // chain prefix, so no tap is computed once for several masks
+#pragma unroll
+                for (int d = 0; d < 8; ++d) {
+                    const int j = (i + d) % 8;
+                    acc = (d == 0 || d == 1 || d == 7) ? mad_w5(P[j], acc) : mad_wm3(P[j], acc);
+                }
+                S[i] = acc;
+            }
+        } else {
+            S[0] = col[a + 1];           // E   column to the right
+            S[1] = Vt[a + 1] + t.X[a];   // NE  E + NE + N
+            S[2] = t.R[c];               // N   row above
+            S[3] = Vt[a - 1] + t.X[a];   // NW  N + NW + W
+            S[4] = col[a - 1];           // W   column to the left
+            S[5] = Vb[a - 1] + b.X[a];   // SW  W + SW + S
+            S[6] = b.R[c];               // S   row below
+            S[7] = Vb[a + 1] + b.X[a];   // SE  S + SE + E
+            if constexpr (MODE == RANK_MAGNITUDE) {
+                // the sums are 8 * S_i and 8 * T (scaled rows); 3 * T is
+                // ((8 * T) >> 3) * 3 (the low 3 bits of each field are 0, so
+                // the shift moves nothing across fields), and
+                // |m_i| = |8 * S_i - 3 * T| = max - min per field
+                const uint32_t T8 = col[a + 1] + col[a - 1] + t.X[a] + b.X[a];
+                const uint32_t T1 = T8 >> 3;
+                const u16x2 T3 = V((T1 << 1) + T1);
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+                    S[i] = U(vmax(V(S[i]), T3)) - U(vmin(V(S[i]), T3));
+            }
+        }
+        u16x2 Sv[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            Sv[i] = V(S[i]);
+        bias = 0x80008000u - U(kth_largest<K>(Sv));  // 0x8000 - threshold per field
+    }
+}
+
 // Codes of the lane's 8 pixels for the code row whose image rows are t
 // (above), m (centre) and b (below).  Vt[a] = X_t[a] + X_m[a] and
 // Vb[a] = X_m[a] + X_b[a] are the vertical pair sums.  Returns the codes of
 // pixels 0..3 in `lo` and 4..7 in `hi` (byte p = pixel p).
 template <int K, int MODE>
-__device__ __forceinline__ void code_row(const Row &t, const Row &b, const uint32_t (&Vt)[6],
-                                         const uint32_t (&Vb)[6], uint32_t &lo, uint32_t &hi)
+__device__ __forceinline__ void code_row(const Row &t, const Row &m, const Row &b,
+                                         const uint32_t (&Vt)[6], const uint32_t (&Vb)[6],
+                                         uint32_t &lo, uint32_t &hi)
 {
-    if constexpr (K == 8) {
+    if constexpr (K == 8 && MODE != CODE_LBP) {
         // the 8th largest is the minimum: every response reaches it
         lo = hi = 0xFFFFFFFFu;
         return;
@@ -213,38 +313,12 @@ __device__ __forceinline__ void code_row(const Row &t, const Row &b, const uint3
         for (int h = 0; h < 2; ++h) {
             uint32_t S[2][8], bias[2];
 #pragma unroll
-            for (int e = 0; e < 2; ++e) {
-                const int c = 2 * h + e, a = c + 1;
-                S[e][0] = col[a + 1];           // E   column to the right
-                S[e][1] = Vt[a + 1] + t.X[a];   // NE  E + NE + N
-                S[e][2] = t.R[c];               // N   row above
-                S[e][3] = Vt[a - 1] + t.X[a];   // NW  N + NW + W
-                S[e][4] = col[a - 1];           // W   column to the left
-                S[e][5] = Vb[a - 1] + b.X[a];   // SW  W + SW + S
-                S[e][6] = b.R[c];               // S   row below
-                S[e][7] = Vb[a + 1] + b.X[a];   // SE  S + SE + E
-                if constexpr (MODE == RANK_MAGNITUDE) {
-                    // the sums are 8 * S_i and 8 * T (scaled rows); 3 * T is
-                    // ((8 * T) >> 3) * 3 (the low 3 bits of each field are 0,
-                    // so the shift moves nothing across fields), and
-                    // |m_i| = |8 * S_i - 3 * T| = max - min per field
-                    const uint32_t T8 = col[a + 1] + col[a - 1] + t.X[a] + b.X[a];
-                    const uint32_t T1 = T8 >> 3;
-                    const u16x2 T3 = V((T1 << 1) + T1);
-#pragma unroll
-                    for (int i = 0; i < 8; ++i)
-                        S[e][i] = U(vmax(V(S[e][i]), T3)) - U(vmin(V(S[e][i]), T3));
-                }
-                u16x2 Sv[8];
-#pragma unroll
-                for (int i = 0; i < 8; ++i)
-                    Sv[i] = V(S[e][i]);
-                bias[e] = 0x80008000u - U(kth_largest<K>(Sv));  // 0x8000 - thr per field
-            }
-            // bit 15 of a field of S_i + bias is set iff S_i >= thr; v_perm_b32
-            // turns the four sign bits of a direction into byte masks
-            // [first pair lo, second pair lo, first hi, second hi], and bit i of
-            // every byte is taken from direction i.
+            for (int e = 0; e < 2; ++e)
+                pair_values<K, MODE>(t, m, b, Vt, Vb, col, 2 * h + e, S[e], bias[e]);
+            // bit 15 of a field of S_i + bias is set iff S_i >= threshold;
+            // v_perm_b32 turns the four sign bits of a direction into byte
+            // masks [first pair lo, second pair lo, first hi, second hi], and
+            // bit i of every byte is taken from direction i.
             uint32_t acc = __builtin_amdgcn_perm(S[1][0] + bias[1], S[0][0] + bias[0], 0x0B090A08u);
 #pragma unroll
             for (int i = 1; i < 8; ++i) {

@@ -155,7 +155,7 @@ __device__ __forceinline__ void step(const ImgView &im, uint32_t *lds_bins, Walk
     for (int a = 0; a < 6; ++a)
         Vb[a] = m.X[a] + b.X[a];
     uint32_t lo, hi;
-    code_row<K, MODE>(t, b, Vt, Vb, lo, hi);
+    code_row<K, MODE>(t, m, b, Vt, Vb, lo, hi);
     if constexpr (CODES) {
         // dword stores at any byte offset (the target allows unaligned access)
         __builtin_amdgcn_raw_buffer_store_b32(lo, im.crsrc, (int)w.coff, 0, 0);
@@ -264,7 +264,7 @@ __device__ void run_task_narrow(const ImgView &im, uint32_t *lds_bins, uint32_t 
         for (int a = 0; a < 6; ++a)
             Vb[a] = m.X[a] + b.X[a];
         uint32_t lo, hi;
-        code_row<K, MODE>(t, b, Vt, Vb, lo, hi);
+        code_row<K, MODE>(t, m, b, Vt, Vb, lo, hi);
         if constexpr (CODES) {
             const uint32_t coff = (uint32_t)r * (uint32_t)im.Wc;
             for (int p = 0; p < nvalid; ++p)

@@ -29,10 +29,19 @@ inline int check_cells(int32_t H, int32_t W, int32_t cells_y, int32_t cells_x)
     return LDP_OK;
 }
 
-inline bool flags_ok(int32_t flags) { return (flags & ~LDP_FLAGS_ALL) == 0; }
+// At most one flag: the variants exclude each other.
+inline bool flags_ok(int32_t flags)
+{
+    return flags == 0 || flags == LDP_RANK_MAGNITUDE || flags == LDP_DIRECT_MASKS ||
+           flags == LDP_CODE_LBP;
+}
 
-// Ranking mode of the kernels (ldp_device.hpp) for the public flags.
-inline int rank_mode(int32_t flags) { return (flags & LDP_RANK_MAGNITUDE) ? 1 : 0; }
+// Kernel mode (ldp_device.hpp: RANK_SIGNED 0, RANK_MAGNITUDE 1, DIRECT_MASKS 2,
+// CODE_LBP 3) for valid public flags.
+inline int rank_mode(int32_t flags)
+{
+    return flags == LDP_RANK_MAGNITUDE ? 1 : flags == LDP_DIRECT_MASKS ? 2 : flags == LDP_CODE_LBP ? 3 : 0;
+}
 
 // Largest cells_x the fused kernels keep in LDS (one cell row, 1 KiB per
 // cell, plus a discard cell).

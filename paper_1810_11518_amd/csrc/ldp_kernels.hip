@@ -101,22 +101,28 @@ __global__ void __launch_bounds__(1024) fused_kernel(const uint8_t *__restrict__
 }
 
 // ---------------------------------------------------------------- dispatch
-// F<K, MODE, FLAG>::launch(args...) for k in 1..8, the ranking mode and a flag.
+// F<K, MODE, FLAG>::launch(args...) for k in 1..8, the kernel mode and a flag
+// (LBP codes do not depend on k: one instantiation).
 template <template <int, int, bool> class F, typename... Args>
 static hipError_t dispatch(int k, int mode, bool flag, Args &&...args)
 {
+    if (mode == CODE_LBP)
+        return flag ? F<1, CODE_LBP, true>::launch(args...) : F<1, CODE_LBP, false>::launch(args...);
+#define LDP_MODE(KK, MM)                                                                    \
+    case MM:                                                                                \
+        return flag ? F<KK, MM, true>::launch(args...) : F<KK, MM, false>::launch(args...);
 #define LDP_CASE(KK)                                                                        \
     case KK:                                                                                \
-        if (mode == RANK_MAGNITUDE)                                                         \
-            return flag ? F<KK, RANK_MAGNITUDE, true>::launch(args...)                      \
-                        : F<KK, RANK_MAGNITUDE, false>::launch(args...);                    \
-        return flag ? F<KK, RANK_SIGNED, true>::launch(args...)                             \
-                    : F<KK, RANK_SIGNED, false>::launch(args...);
+        switch (mode) {                                                                     \
+            LDP_MODE(KK, RANK_SIGNED) LDP_MODE(KK, RANK_MAGNITUDE) LDP_MODE(KK, DIRECT_MASKS) \
+        }                                                                                   \
+        break;
     switch (k) {
         LDP_CASE(1) LDP_CASE(2) LDP_CASE(3) LDP_CASE(4)
         LDP_CASE(5) LDP_CASE(6) LDP_CASE(7) LDP_CASE(8)
     }
 #undef LDP_CASE
+#undef LDP_MODE
     return hipErrorInvalidValue;
 }
 

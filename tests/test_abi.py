@@ -65,10 +65,11 @@ def test_invalid_arguments_return_before_any_launch(lib):
         assert lib.ldp_batch_plan_create(ctypes.byref(plan), 10, 100, 3, 7, 6, ctypes.byref(t)) == E
     assert lib.ldp_batch_run(None, None) == E
     # variants: unknown flag bits, and the same checks as the plain calls
-    assert lib.ldp_codes_ex(p, 10, 10, 10, 3, 2, p, None) == E
-    assert lib.ldp_codes_ex(p, 10, 10, 10, 3, -1, p, None) == E
+    for bad_flags in (3, 5, 6, 7, 8, -1):  # one flag at most, and only known ones
+        assert lib.ldp_codes_ex(p, 10, 10, 10, 3, bad_flags, p, None) == E
+    assert lib.ldp_codes_ex(p, 10, 10, 10, 0, binding.LDP_CODE_LBP, p, None) == E  # k still checked
     assert lib.ldp_codes_ex(p, 10, 10, 9, 3, binding.LDP_RANK_MAGNITUDE, p, None) == E
-    assert lib.ldp_extract_ex(p, 10, 10, 10, 3, 4, 1, 1, p, p, None) == E
+    assert lib.ldp_extract_ex(p, 10, 10, 10, 3, 8, 1, 1, p, p, None) == E
     assert lib.ldp_extract_ex(p, 10, 10, 10, 9, 1, 1, 1, p, p, None) == E
     assert lib.ldp_batch_plan_create_ex(ctypes.byref(plan), 10, 100, 3, 8, 7, 6, None) == E
     assert lib.ldp_compact_histograms(p, 5, 0, p, None) == E

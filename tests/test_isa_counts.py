@@ -60,7 +60,9 @@ def test_valu_per_row_step_matches_generated_code(tmp_path):
     p = subprocess.run(cmd, capture_output=True, text=True)
     assert p.returncode == 0, p.stderr[-2000:]
     asm = open(out).read()
-    for mode, table in ((0, bench.VALU_PER_ROW_STEP), (1, bench.VALU_PER_ROW_STEP_MAGNITUDE)):
+    for mode, table in ((0, bench.VALU_PER_ROW_STEP), (1, bench.VALU_PER_ROW_STEP_MAGNITUDE),
+                        (2, bench.VALU_PER_ROW_STEP_DIRECT)):
         for k in range(1, 9):
             n = main_loop_valu(asm, k, mode)
             assert table[k] * 3 == pytest.approx(n), (mode, k, n)
+    assert bench.VALU_PER_ROW_STEP_LBP * 3 == pytest.approx(main_loop_valu(asm, 1, 3))

@@ -1,5 +1,6 @@
-"""Parity of the variant paths (ranking by response magnitude, Eq. 6 compact
-histograms) through the C ABI with the CPU oracle: bit-exact."""
+"""Parity of the variant paths through the C ABI with the CPU oracle,
+bit-exact: ranking by response magnitude, Eq. 6 compact histograms, the
+unaccelerated direct-mask route (same codes as Eq. 2) and LBP labels."""
 import math
 
 import numpy as np
@@ -116,3 +117,65 @@ def test_compact_histograms_many_cells_and_odd_counts(lib):
         h = r.integers(0, 1 << 20, (n, 256)).astype(np.int32)
         got = lib.compact_histograms(_dev(h), 3).cpu().numpy().view(np.uint32)
         assert (got == oracle_np.compact_histograms(h.view(np.uint32), 3)).all(), n
+
+
+# ------------------------------------------------------------ direct masks, LBP
+
+@pytest.mark.parametrize("k", range(1, 9))
+def test_direct_masks_give_the_signed_codes(lib, k):
+    """The unaccelerated route (each response its own 8-tap correlation) must
+    give exactly the codes of Eq. 2 as the oracle computes them."""
+    for img in _imgs():
+        got = lib.codes(_dev(img), k, flags=lib.LDP_DIRECT_MASKS).cpu().numpy()
+        want = oracle_np.ldp_codes(img, k) if img.size < 20000 else oracle_c.ldp_codes(img, k)
+        assert (got == want).all(), (img.shape, k)
+
+
+def test_lbp_codes_match_oracle(lib):
+    from oracle import lbp as oracle_lbp
+    imgs = _imgs() + [np.full((40, 37), 77, np.uint8)]
+    for img in imgs:
+        for k in (1, 3, 8):  # k is ignored for LBP
+            got = lib.codes(_dev(img), k, flags=lib.LDP_CODE_LBP).cpu().numpy()
+            assert (got == oracle_lbp.lbp_codes(img)).all(), (img.shape, k)
+
+
+@pytest.mark.parametrize("cells", [(7, 6), (4, 70)])
+@pytest.mark.parametrize("mode", ["lbp", "direct"])
+def test_lbp_and_direct_extract_match_oracle(lib, cells, mode):
+    from oracle import lbp as oracle_lbp
+    for img in [synth.workload_image("single", 0), synth.image(synth.KIND_BLUR_SP_FLAT, 3, 4, 211, 290)]:
+        if mode == "lbp":
+            wc = oracle_lbp.lbp_codes(img)
+            flags = lib.LDP_CODE_LBP
+        else:
+            wc = oracle_c.ldp_codes(img, 3)
+            flags = lib.LDP_DIRECT_MASKS
+        wh = oracle_np.ldp_histograms(wc, *cells)
+        c, h = lib.extract(_dev(img), 3, *cells, flags=flags)
+        assert (c.cpu().numpy() == wc).all()
+        assert (h.cpu().numpy().view(np.uint32) == wh).all()
+
+
+@pytest.mark.parametrize("mode", ["lbp", "direct"])
+def test_lbp_and_direct_batch_plans_match_oracle(lib, mode):
+    from oracle import lbp as oracle_lbp
+    r = np.random.default_rng(88)
+    n = 30
+    cells = (7, 6)
+    Hs, Ws = r.integers(9, 260, n), r.integers(8, 420, n)
+    Ws[:2] = [640, 9]
+    b = Batch(Hs, Ws, synth.KIND_BLUR_SP_FLAT, 89, cells)
+    pixels = int((b.Hs.astype(np.int64) * b.Ws).sum())
+    flags = lib.LDP_CODE_LBP if mode == "lbp" else lib.LDP_DIRECT_MASKS
+    plan = lib.BatchPlan(n, pixels, 3, cells[0], cells[1], flags=flags)
+    plan.set(lib.BatchPlan.descs(*b.descs_args))
+    plan.run()
+    torch.cuda.synchronize()
+    for j in range(n):
+        img = b.image(j)
+        wc = oracle_lbp.lbp_codes(img) if mode == "lbp" else oracle_c.ldp_codes(img, 3)
+        wh = oracle_np.ldp_histograms(wc, *cells)
+        assert (b.codes[j].cpu().numpy().reshape(wc.shape) == wc).all(), j
+        assert (b.hist[j].cpu().numpy().view(np.uint32).reshape(wh.shape) == wh).all(), j
+    plan.close()
