@@ -49,32 +49,53 @@ constexpr int32_t compact_patterns(int k)
     return n;
 }
 
+#ifndef LDP_COMPACT_CELLS_PER_WAVE
+#define LDP_COMPACT_CELLS_PER_WAVE 4
+#endif
+#ifndef LDP_COMPACT_MAX_BLOCKS
+#define LDP_COMPACT_MAX_BLOCKS 8192
+#endif
+
+// Each wave takes LDP_COMPACT_CELLS_PER_WAVE consecutive cells per round and
+// issues all their loads before using them (more loads in flight).
 __global__ void __launch_bounds__(256) compact_kernel(const uint32_t *__restrict__ hist,
                                                       int64_t n_cells, int32_t k, int32_t npat,
                                                       uint32_t *__restrict__ out)
 {
+    constexpr int C = LDP_COMPACT_CELLS_PER_WAVE;
     const int lane = threadIdx.x & 63;
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
-    for (int64_t cell = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-         cell < n_cells; cell += waves) {
-        const uint32_t *h = hist + cell * 256;
-        uint32_t *o = out + cell * (npat + 1);
-        uint32_t rest = 0;
+    int b[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int code = lane + 64 * q;
-            const uint32_t v = h[code];
-            const int b = kCompact.bin[k][code];
-            if (b < npat)
-                o[b] = v;
-            else
-                rest += v;
+    for (int q = 0; q < 4; ++q)
+        b[q] = kCompact.bin[k][lane + 64 * q];
+    for (int64_t c0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * C;
+         c0 < n_cells; c0 += waves * C) {
+        uint32_t v[C][4];
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                v[c][q] = c0 + c < n_cells ? hist[(c0 + c) * 256 + lane + 64 * q] : 0u;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            if (c0 + c >= n_cells)
+                break;
+            uint32_t *o = out + (c0 + c) * (npat + 1);
+            uint32_t rest = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (b[q] < npat)
+                    o[b[q]] = v[c][q];
+                else
+                    rest += v[c][q];
+            }
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1)
+                rest += __shfl_xor(rest, off);
+            if (lane == 0)
+                o[npat] = rest;
         }
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1)
-            rest += __shfl_xor(rest, off);
-        if (lane == 0)
-            o[npat] = rest;
     }
 }
 
@@ -97,8 +118,9 @@ int ldp_compact_histograms(const uint32_t *hist, int64_t n_cells, int32_t k, uin
     if (n_cells == 0)
         return LDP_OK;
     const int32_t npat = ldp::compact_patterns(k);
-    // one cell per wave (a loop only beyond 2^20 workgroups): many loads in flight
-    const int64_t blocks = std::min<int64_t>((n_cells + 3) / 4, int64_t(1) << 20);
+    const int64_t cells_per_block = 4 * LDP_COMPACT_CELLS_PER_WAVE;
+    const int64_t blocks =
+        std::min<int64_t>((n_cells + cells_per_block - 1) / cells_per_block, LDP_COMPACT_MAX_BLOCKS);
     hipLaunchKernelGGL(ldp::compact_kernel, dim3((unsigned)blocks), dim3(256), 0,
                        (hipStream_t)stream, hist, n_cells, k, npat, out);
     return hipGetLastError() == hipSuccess ? LDP_OK : LDP_ERR_HIP;
