@@ -154,6 +154,35 @@ def variant_bench(binding, torch, args, plan_args, descs, hist, codes, code_off,
                      "peak": round(VALU_PEAK_T, 2),
                      "frac": round(lane_ops / (ms * 1e-3) / 1e12 / VALU_PEAK_T, 4),
                      "per_pixel": round(VALU_PER_ROW_STEP_MAGNITUDE[k] / 8.0, 2)}}
+    # windows of w x w code pixels instead of the cell grid (Section 3.2), as
+    # batch plans over the same images; the histograms grow as windows shrink
+    wins = []
+    max_w = int(Ws.max())
+    for w in (20, 25, 50, 100):
+        if -(-(max_w - 2) // w) > 63:
+            continue
+        ny = -(-(Hs.astype(np.int64) - 2) // w)
+        nx = -(-(Ws.astype(np.int64) - 2) // w)
+        nbins = ny * nx * 256
+        whist = torch.empty(int(nbins.sum()), dtype=torch.int32, device=hist.device)
+        hoff = np.concatenate([[0], np.cumsum(nbins)])[:-1] * 4
+        wdescs = binding.BatchPlan.descs([int(d.img) for d in descs], [int(d.codes) for d in descs],
+                                         [whist.data_ptr() + int(o) for o in hoff],
+                                         [int(d.stride) for d in descs], [int(d.H) for d in descs],
+                                         [int(d.W) for d in descs])
+        plan = binding.BatchPlan(n, pixels, k, w, w, tune, windows=True, max_width=max_w)
+        plan.set(wdescs)
+        ms = _timed(torch, plan.run, args.variant_steps)
+        plan.close()
+        wb = int((Hs.astype(np.int64) * Ws).sum() + code_pixels + nbins.sum() * 4)
+        wins.append({"window": w, "windows": int((ny * nx).sum()), "ms": round(ms, 4),
+                     "value": round(pixels / (ms * 1e-3) / 1e6, 1), "unit": "Mpixel/s",
+                     "hbm": {"achieved": round(wb / (ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                             "unit": "GB/s", "frac": round(wb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                             "algorithmic_bytes": wb}})
+        del whist
+    out["windows"] = {"what": "the batch with w x w pixel windows instead of the cell grid "
+                              "(batch plans with windows)", "runs": wins}
     abytes = algorithmic_bytes(Hs, Ws, cells)
     for name, flag, per_step, what in (
             ("direct_masks", binding.LDP_DIRECT_MASKS, VALU_PER_ROW_STEP_DIRECT[k],

@@ -155,6 +155,34 @@ int32_t ldp_compact_bins(int32_t k);
 int ldp_compact_histograms(const uint32_t *hist, int64_t n_cells, int32_t k, uint32_t *out,
                            ldp_stream_t stream);
 
+/* ---------------------------------------------------------------- windows
+ *
+ * Histograms per window instead of per grid cell (Section 3.2 extracts
+ * features over windows of 10x10 .. 100x100 pixels): non-overlapping windows
+ * of win_y x win_x code pixels tile the code map from its first row and
+ * column; the last row and column of windows are cut at the map's edge
+ * (ny = ceil((H-2)/win_y), nx = ceil((W-2)/win_x) windows; a 280x280 image
+ * with 10x10 windows has 28 x 28 = 784, as Table 3 lists).  Window (wy, wx)
+ * is at hist[(wy*nx + wx)*256 + code]; win_y, win_x >= 1 (sides larger than
+ * the map count as the map).
+ */
+
+/* ldp_window_grid -- ny and nx for an H x W image (either pointer may be
+ * NULL).  Errors: LDP_ERR_INVALID_ARG for sizes out of range. */
+int ldp_window_grid(int32_t H, int32_t W, int32_t win_y, int32_t win_x, int32_t *ny, int32_t *nx);
+
+/* ldp_histograms_windows -- ldp_histograms with windows; hist has
+ * ny*nx*256 uint32, overwritten. */
+int ldp_histograms_windows(const uint8_t *codes, int32_t H, int32_t W, int32_t win_y,
+                           int32_t win_x, uint32_t *hist, ldp_stream_t stream);
+
+/* ldp_extract_windows -- ldp_extract_ex with windows.  With nx > 63 the
+ * histograms are counted in a second pass over the code map, so `codes` must
+ * not be NULL then (LDP_ERR_UNSUPPORTED). */
+int ldp_extract_windows(const uint8_t *img, int32_t H, int32_t W, int64_t stride, int32_t k,
+                        int32_t flags, int32_t win_y, int32_t win_x, uint8_t *codes,
+                        uint32_t *hist, ldp_stream_t stream);
+
 /* ---------------------------------------------------------------- batches
  *
  * Many images of any sizes in ONE persistent launch: the work (row bands of
@@ -208,6 +236,15 @@ int ldp_batch_plan_create(ldp_batch_plan **plan, int32_t max_images, int64_t max
 int ldp_batch_plan_create_ex(ldp_batch_plan **plan, int32_t max_images, int64_t max_pixels,
                              int32_t k, int32_t flags, int32_t cells_y, int32_t cells_x,
                              const ldp_tune *tune);
+
+/* A plan whose runs give each image ldp_extract_windows' results (every
+ * image's hist holds its own ny*nx*256 bins).  Images may be at most
+ * max_width columns wide (wider ones: LDP_ERR_INVALID_ARG from set);
+ * ceil((max_width-2)/win_x) must be <= 63, else LDP_ERR_UNSUPPORTED.  The
+ * plan's device work table grows when a batch needs more work items. */
+int ldp_batch_plan_create_windows(ldp_batch_plan **plan, int32_t max_images, int64_t max_pixels,
+                                  int32_t max_width, int32_t k, int32_t flags, int32_t win_y,
+                                  int32_t win_x, const ldp_tune *tune);
 
 /*
  * ldp_batch_plan_set -- (re)load the batch: `descs` is a HOST array of n

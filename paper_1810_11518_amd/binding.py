@@ -29,7 +29,9 @@ LDP_CODE_LBP = 4
 EXPORTED = [
     "ldp_status_string", "ldp_version", "ldp_codes", "ldp_histograms", "ldp_extract",
     "ldp_codes_ex", "ldp_extract_ex", "ldp_compact_bins", "ldp_compact_histograms",
-    "ldp_batch_plan_create", "ldp_batch_plan_create_ex", "ldp_batch_plan_set", "ldp_batch_run", "ldp_batch_run_per_image",
+    "ldp_window_grid", "ldp_histograms_windows", "ldp_extract_windows",
+    "ldp_batch_plan_create", "ldp_batch_plan_create_ex", "ldp_batch_plan_create_windows",
+    "ldp_batch_plan_set", "ldp_batch_run", "ldp_batch_run_per_image",
     "ldp_batch_plan_info", "ldp_batch_plan_destroy",
     "ldp_now", "ldp_server_create", "ldp_server_submit", "ldp_server_poll",
     "ldp_server_stats_get", "ldp_server_destroy",
@@ -126,6 +128,12 @@ def load():
                                                  ctypes.POINTER(Tune)]),
         "ldp_batch_plan_create_ex": (ctypes.c_int, [ctypes.POINTER(p), i32, i64, i32, i32, i32,
                                                     i32, ctypes.POINTER(Tune)]),
+        "ldp_batch_plan_create_windows": (ctypes.c_int, [ctypes.POINTER(p), i32, i64, i32, i32,
+                                                         i32, i32, i32, ctypes.POINTER(Tune)]),
+        "ldp_window_grid": (ctypes.c_int, [i32, i32, i32, i32, ctypes.POINTER(i32),
+                                           ctypes.POINTER(i32)]),
+        "ldp_histograms_windows": (ctypes.c_int, [p, i32, i32, i32, i32, p, p]),
+        "ldp_extract_windows": (ctypes.c_int, [p, i32, i32, i64, i32, i32, i32, i32, p, p, p]),
         "ldp_batch_plan_set": (ctypes.c_int, [p, ctypes.POINTER(ImageDesc), i32, p]),
         "ldp_batch_run": (ctypes.c_int, [p, p]),
         "ldp_batch_run_per_image": (ctypes.c_int, [p, p]),
@@ -220,6 +228,46 @@ def extract(img, k, cells_y, cells_x, want_codes=True, codes_out=None, hist_out=
     return (codes_out if want_codes else None), hist_out
 
 
+def window_grid(H, W, win_y, win_x):
+    """(ny, nx): windows over the (H-2) x (W-2) code map."""
+    ny, nx = ctypes.c_int32(), ctypes.c_int32()
+    _check(load().ldp_window_grid(H, W, win_y, win_x, ctypes.byref(ny), ctypes.byref(nx)),
+           "ldp_window_grid")
+    return int(ny.value), int(nx.value)
+
+
+def extract_windows(img, k, win_y, win_x, want_codes=True, codes_out=None, hist_out=None,
+                    stream=None, flags=0):
+    """Codes and per-window histograms: (codes or None, hist (ny, nx, 256))."""
+    import torch
+    ptr, H, W, stride = _image_args(img)
+    ny, nx = window_grid(H, W, win_y, win_x)
+    if want_codes and codes_out is None:
+        codes_out = torch.empty((H - 2, W - 2), dtype=torch.uint8, device=img.device)
+    if hist_out is None:
+        hist_out = torch.empty((ny, nx, 256), dtype=torch.int32, device=img.device)
+    cptr = codes_out.data_ptr() if want_codes else None
+    _check(load().ldp_extract_windows(ptr, H, W, stride, k, flags, win_y, win_x, cptr,
+                                      hist_out.data_ptr(), _stream(stream)),
+           "ldp_extract_windows")
+    return (codes_out if want_codes else None), hist_out
+
+
+def histograms_windows(code_map, win_y, win_x, out=None, stream=None):
+    """Per-window histograms of a dense code map: int32 (ny, nx, 256)."""
+    import torch
+    if code_map.dtype != torch.uint8 or code_map.dim() != 2 or not code_map.is_contiguous():
+        raise ValueError("code map must be a contiguous 2-D torch.uint8 tensor")
+    Hc, Wc = code_map.shape
+    ny, nx = window_grid(Hc + 2, Wc + 2, win_y, win_x)
+    if out is None:
+        out = torch.empty((ny, nx, 256), dtype=torch.int32, device=code_map.device)
+    _check(load().ldp_histograms_windows(code_map.data_ptr(), Hc + 2, Wc + 2, win_y, win_x,
+                                         out.data_ptr(), _stream(stream)),
+           "ldp_histograms_windows")
+    return out
+
+
 def compact_bins(k):
     """C(8, k) + 1: bins of Eq. 6's compact vector plus the tie bin."""
     n = load().ldp_compact_bins(k)
@@ -247,15 +295,24 @@ def compact_histograms(hist, k, out=None, stream=None):
 class BatchPlan:
     """A persistent, graph-captured launch over many images (ldp_batch_*)."""
 
-    def __init__(self, max_images, max_pixels, k, cells_y, cells_x, tune=None, flags=0):
+    def __init__(self, max_images, max_pixels, k, cells_y, cells_x, tune=None, flags=0,
+                 windows=False, max_width=None):
+        """cells_y x cells_x cells, or with ``windows`` windows of cells_y x
+        cells_x code pixels over images at most ``max_width`` wide."""
         self._lib = load()
         self._plan = ctypes.c_void_p()
         t = make_tune(tune) if tune is not None else None
-        _check(self._lib.ldp_batch_plan_create_ex(ctypes.byref(self._plan), max_images,
-                                                  max_pixels, k, flags, cells_y, cells_x,
-                                                  ctypes.byref(t) if t is not None else None),
-               "ldp_batch_plan_create_ex")
-        self.k, self.cells, self.flags = k, (cells_y, cells_x), flags
+        tp = ctypes.byref(t) if t is not None else None
+        if windows:
+            _check(self._lib.ldp_batch_plan_create_windows(ctypes.byref(self._plan), max_images,
+                                                           max_pixels, max_width, k, flags,
+                                                           cells_y, cells_x, tp),
+                   "ldp_batch_plan_create_windows")
+        else:
+            _check(self._lib.ldp_batch_plan_create_ex(ctypes.byref(self._plan), max_images,
+                                                      max_pixels, k, flags, cells_y, cells_x, tp),
+                   "ldp_batch_plan_create_ex")
+        self.k, self.cells, self.flags, self.windows = k, (cells_y, cells_x), flags, windows
 
     @staticmethod
     def descs(imgs, codes, hists, strides=None, Hs=None, Ws=None):

@@ -22,45 +22,78 @@ namespace ldp {
 
 struct Item {
     int32_t img;        // index into the descriptor table
-    int16_t cy0, cy1;   // cell rows [cy0, cy1)
+    uint16_t cy0, cy1;  // cell rows [cy0, cy1) (at most 65534 cell rows)
     int32_t min_rows;   // target code rows per lane task
 };
 
-__global__ void clear_counter_kernel(uint32_t *meta) { meta[1] = 0; }
+// Device meta words of a plan: [0] item count, [1] queue counter, [2..3] the
+// item table's address (the table can grow when a new batch is loaded
+// without re-capturing the graph).
+struct Meta {
+    uint32_t n_items, next;
+    const Item *items;
+};
 
+__global__ void clear_counter_kernel(Meta *meta) { meta->next = 0; }
+
+// At least 5 waves per SIMD: at most 96 VGPRs (allocated in steps of 8), the
+// occupancy the batch kernel is tuned for (4 waves measure ~17% slower).
 #ifndef LDP_BATCH_ATTR
-#define LDP_BATCH_ATTR
+#define LDP_BATCH_ATTR __attribute__((amdgpu_waves_per_eu(5)))
 #endif
 
+typedef __attribute__((address_space(4))) const Item ConstItem;  // read-only while a kernel runs
+
+__device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint64_t uniform64(uint64_t v)
+{
+    return ((uint64_t)uniform((uint32_t)(v >> 32)) << 32) | uniform((uint32_t)v);
+}
+
+// (gy, gx): cells_y x cells_x cells, or with `windows` window sides in code
+// pixels (every image's cell grid follows from its own size).
 template <int K, int MODE>
 __global__ void __launch_bounds__(1024) LDP_BATCH_ATTR batch_kernel(const ldp_image_desc *__restrict__ descs,
-                                                     const Item *__restrict__ items,
-                                                     uint32_t *meta, int32_t cells_y,
-                                                     int32_t cells_x)
+                                                     Meta *meta, int32_t gy, int32_t gx,
+                                                     int32_t windows)
 {
     extern __shared__ uint32_t lds[];
     __shared__ uint32_t s_item;
-    const uint32_t n_items = meta[0];
+    // the item count and table address are the same for every lane:
+    // readfirstlane keeps them (and what is read through them) in scalar
+    // registers, which the buffer descriptors built from them must be in
+    const uint32_t n_items = uniform(meta->n_items);
+    const ConstItem *items =
+        (const ConstItem *)(uintptr_t)uniform64(reinterpret_cast<uint64_t>(meta->items));
     for (;;) {
         if (threadIdx.x == 0)
-            s_item = atomicAdd(&meta[1], 1u);
+            s_item = atomicAdd(&meta->next, 1u);
         __syncthreads();
-        const uint32_t it = s_item;
+        const uint32_t it = uniform(s_item);
         __syncthreads();
         if (it >= n_items)
             break;
-        const Item w = items[it];
+        // the item table does not change while the kernel runs: read through
+        // the constant address space, the item (and the descriptor it
+        // indexes) arrives in scalar registers
+        const ConstItem &ci = items[it];
+        Item w;
+        w.img = ci.img;
+        w.cy0 = ci.cy0;
+        w.cy1 = ci.cy1;
+        w.min_rows = ci.min_rows;
         const ldp_image_desc d = descs[w.img];
+        uint32_t *hist = d.hist;
         ImgView im = make_view(d.img, d.stride, d.H, d.W, d.codes);
-        const int32_t r0 = cell_start(w.cy0, im.Hc, cells_y);
-        const int32_t r1 = cell_start(w.cy1, im.Hc, cells_y);
+        const Geom geo = make_geom(im.Hc, im.Wc, gy, gx, windows != 0);
+        const int32_t r0 = geom_row_start(geo, w.cy0, im.Hc);
+        const int32_t r1 = geom_row_start(geo, w.cy1, im.Hc);
         // a null code pointer gives an empty store range: stores are dropped
-        fused_item<K, MODE, true>(im, lds, cells_y, cells_x, w.cy0, w.cy1, r0, r1, d.hist, false,
-                            w.min_rows);
+        fused_item<K, MODE, true>(im, lds, geo, w.cy0, w.cy1, r0, r1, hist, false, w.min_rows);
     }
 }
 
-typedef void (*batch_fn)(const ldp_image_desc *, const Item *, uint32_t *, int32_t, int32_t);
+typedef void (*batch_fn)(const ldp_image_desc *, Meta *, int32_t, int32_t, int32_t);
 
 template <int MODE>
 static batch_fn batch_kernel_for_mode(int k)
@@ -91,7 +124,10 @@ static batch_fn batch_kernel_for(int k, int mode)
 }  // namespace ldp
 
 struct ldp_batch_plan {
-    int32_t k = 3, flags = 0, cells_y = 1, cells_x = 1, max_images = 0;
+    int32_t k = 3, flags = 0, max_images = 0;
+    int32_t gy = 1, gx = 1;  // cells_y, cells_x, or window sides when `windows`
+    bool windows = false;
+    int32_t nx_max = 1;      // most cell columns of an image (LDS sizing)
     int64_t max_pixels = 0, max_items = 0;
     int32_t threads = 256, grid = 0;
     int32_t n_classes = 1;
@@ -100,10 +136,10 @@ struct ldp_batch_plan {
     int device = 0;
     ldp_image_desc *d_descs = nullptr;
     ldp::Item *d_items = nullptr;
-    uint32_t *d_meta = nullptr;  // [0] item count, [1] queue counter
+    ldp::Meta *d_meta = nullptr;
     ldp_image_desc *h_descs = nullptr;  // pinned staging
     ldp::Item *h_items = nullptr;       // pinned staging
-    uint32_t *h_meta = nullptr;         // pinned staging
+    ldp::Meta *h_meta = nullptr;        // pinned staging
     std::vector<ldp_image_desc> descs;  // the loaded batch
     int64_t n_items = 0;
     hipStream_t cap_stream = nullptr;
@@ -133,24 +169,24 @@ void release(ldp_batch_plan *p)
 
 }  // namespace
 
-extern "C" {
+namespace {
 
-int ldp_batch_plan_create_ex(ldp_batch_plan **out, int32_t max_images, int64_t max_pixels,
-                             int32_t k, int32_t flags, int32_t cells_y, int32_t cells_x,
-                             const ldp_tune *tune)
+// Shared by the cell-grid and window plans; nx_max bounds an image's cell
+// columns (the LDS of an item holds its cell rows of nx_max + 1 cells).
+int create_plan(ldp_batch_plan **out, int32_t max_images, int64_t max_pixels, int32_t k,
+                int32_t flags, bool windows, int32_t gy, int32_t gx, int32_t nx_max,
+                const ldp_tune *tune)
 {
-    if (!out || max_images < 1 || max_pixels < 9 || k < 1 || k > 8 || !ldp::flags_ok(flags) ||
-        cells_y < 1 || cells_x < 1 || cells_y > LDP_MAX_SIDE - 2 ||
-        cells_x > ldp::kMaxFusedCellsX)
-        return LDP_ERR_INVALID_ARG;
     *out = nullptr;
     ldp_batch_plan *p = new (std::nothrow) ldp_batch_plan();
     if (!p)
         return LDP_ERR_NO_MEMORY;
     p->k = k;
     p->flags = flags;
-    p->cells_y = cells_y;
-    p->cells_x = cells_x;
+    p->gy = gy;
+    p->gx = gx;
+    p->windows = windows;
+    p->nx_max = nx_max;
     p->max_images = max_images;
     p->max_pixels = max_pixels;
     if (tune) {
@@ -180,24 +216,28 @@ int ldp_batch_plan_create_ex(ldp_batch_plan **out, int32_t max_images, int64_t m
         delete p;
         return LDP_ERR_INVALID_ARG;
     }
-    // an item's cell rows of histograms must fit in 64 KB of LDS (cells_x <= 63
+    // an item's cell rows of histograms must fit in 64 KB of LDS (nx_max <= 63
     // leaves room for at least one)
-    const int32_t lds_cpi = (int32_t)(65536u / ldp::hist_row_bytes(cells_x));
-    int32_t max_cpi = 1, min_cpi = cells_y;
+    const int32_t lds_cpi = (int32_t)(65536u / ldp::hist_row_bytes(nx_max));
+    int32_t max_cpi = 1, min_cpi = windows ? 65535 : gy;
     for (int c = 0; c < p->n_classes; ++c) {
         ldp_size_class &sc = p->classes[c];
         if (sc.cell_rows_per_item < 1 || sc.rows_per_task < 1 || sc.max_pixels < 1) {
             delete p;
             return LDP_ERR_INVALID_ARG;
         }
-        sc.cell_rows_per_item = std::min(std::min(sc.cell_rows_per_item, cells_y), lds_cpi);
+        sc.cell_rows_per_item = std::min(sc.cell_rows_per_item, lds_cpi);
+        if (!windows)
+            sc.cell_rows_per_item = std::min(sc.cell_rows_per_item, gy);
         max_cpi = std::max(max_cpi, sc.cell_rows_per_item);
         min_cpi = std::min(min_cpi, sc.cell_rows_per_item);
     }
     p->classes[p->n_classes - 1].max_pixels = INT64_MAX;
-    p->max_items = (int64_t)max_images * ((cells_y + min_cpi - 1) / min_cpi);
+    // item table: enough for max_images images of a cell grid; window plans
+    // start at 8 items per image and grow when a batch needs more
+    p->max_items = (int64_t)max_images * (windows ? 8 : (gy + min_cpi - 1) / min_cpi);
     // LDS: the largest item's cell rows, each with its discard cell
-    p->lds_bytes = (size_t)max_cpi * ldp::hist_row_bytes(cells_x);
+    p->lds_bytes = (size_t)max_cpi * ldp::hist_row_bytes(nx_max);
     if (hipGetDevice(&p->device) != hipSuccess) {
         delete p;
         return LDP_ERR_HIP;
@@ -208,12 +248,12 @@ int ldp_batch_plan_create_ex(ldp_batch_plan **out, int32_t max_images, int64_t m
     };
     if (hipMalloc(&p->d_descs, sizeof(ldp_image_desc) * max_images) != hipSuccess ||
         hipMalloc(&p->d_items, sizeof(ldp::Item) * p->max_items) != hipSuccess ||
-        hipMalloc(&p->d_meta, 64) != hipSuccess ||
+        hipMalloc(&p->d_meta, sizeof(ldp::Meta)) != hipSuccess ||
         hipHostMalloc(&p->h_descs, sizeof(ldp_image_desc) * max_images) != hipSuccess ||
         hipHostMalloc(&p->h_items, sizeof(ldp::Item) * p->max_items) != hipSuccess ||
-        hipHostMalloc(&p->h_meta, 64) != hipSuccess)
+        hipHostMalloc(&p->h_meta, sizeof(ldp::Meta)) != hipSuccess)
         return fail(LDP_ERR_NO_MEMORY);
-    if (hipMemset(p->d_meta, 0, 64) != hipSuccess)
+    if (hipMemset(p->d_meta, 0, sizeof(ldp::Meta)) != hipSuccess)
         return fail(LDP_ERR_HIP);
 
     ldp::batch_fn fn = ldp::batch_kernel_for(k, ldp::rank_mode(flags));
@@ -234,14 +274,48 @@ int ldp_batch_plan_create_ex(ldp_batch_plan **out, int32_t max_images, int64_t m
         return fail(LDP_ERR_HIP);
     hipLaunchKernelGGL(ldp::clear_counter_kernel, dim3(1), dim3(1), 0, p->cap_stream, p->d_meta);
     hipLaunchKernelGGL(fn, dim3(p->grid), dim3(p->threads), p->lds_bytes, p->cap_stream,
-                       (const ldp_image_desc *)p->d_descs, (const ldp::Item *)p->d_items,
-                       p->d_meta, cells_y, cells_x);
+                       (const ldp_image_desc *)p->d_descs, p->d_meta, gy, gx, windows ? 1 : 0);
     hipError_t ce = hipStreamEndCapture(p->cap_stream, &p->graph);
     if (ce != hipSuccess || hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) !=
                                 hipSuccess)
         return fail(LDP_ERR_HIP);
     *out = p;
     return LDP_OK;
+}
+
+bool common_args_ok(ldp_batch_plan **out, int32_t max_images, int64_t max_pixels, int32_t k,
+                    int32_t flags)
+{
+    return out && max_images >= 1 && max_pixels >= 9 && k >= 1 && k <= 8 && ldp::flags_ok(flags);
+}
+
+}  // namespace
+
+extern "C" {
+
+int ldp_batch_plan_create_ex(ldp_batch_plan **out, int32_t max_images, int64_t max_pixels,
+                             int32_t k, int32_t flags, int32_t cells_y, int32_t cells_x,
+                             const ldp_tune *tune)
+{
+    if (!common_args_ok(out, max_images, max_pixels, k, flags) || cells_y < 1 || cells_x < 1 ||
+        cells_y > LDP_MAX_SIDE - 2 || cells_x > ldp::kMaxFusedCellsX)
+        return LDP_ERR_INVALID_ARG;
+    return create_plan(out, max_images, max_pixels, k, flags, false, cells_y, cells_x, cells_x,
+                       tune);
+}
+
+int ldp_batch_plan_create_windows(ldp_batch_plan **out, int32_t max_images, int64_t max_pixels,
+                                  int32_t max_width, int32_t k, int32_t flags, int32_t win_y,
+                                  int32_t win_x, const ldp_tune *tune)
+{
+    if (!common_args_ok(out, max_images, max_pixels, k, flags) || max_width < 3 ||
+        max_width > LDP_MAX_SIDE || win_y < 1 || win_x < 1)
+        return LDP_ERR_INVALID_ARG;
+    const int32_t wc = max_width - 2, wx = std::min(win_x, wc);
+    const int32_t nx_max = (wc + wx - 1) / wx;
+    if (nx_max > ldp::kMaxFusedCellsX)
+        return LDP_ERR_UNSUPPORTED;
+    return create_plan(out, max_images, max_pixels, k, flags, true, win_y, win_x, nx_max, tune);
 }
 
 int ldp_batch_plan_create(ldp_batch_plan **out, int32_t max_images, int64_t max_pixels, int32_t k,
@@ -263,8 +337,12 @@ int ldp_batch_plan_set(ldp_batch_plan *p, const ldp_image_desc *descs, int32_t n
         int st = ldp::check_image(d.img, d.H, d.W, d.stride);
         if (st != LDP_OK)
             return st;
-        if (!d.hist || d.H - 2 < p->cells_y || d.W - 2 < p->cells_x)
+        if (!d.hist)
             return LDP_ERR_INVALID_ARG;
+        if (!p->windows && (d.H - 2 < p->gy || d.W - 2 < p->gx))
+            return LDP_ERR_INVALID_ARG;
+        if (p->windows && ldp::make_geom(d.H - 2, d.W - 2, p->gy, p->gx, true).nx > p->nx_max)
+            return LDP_ERR_INVALID_ARG;  // wider than the plan's max_width
         pixels += (int64_t)d.H * d.W;
     }
     if (pixels > p->max_pixels)
@@ -283,16 +361,40 @@ int ldp_batch_plan_set(ldp_batch_plan *p, const ldp_image_desc *descs, int32_t n
             ++c;
         const int32_t cpi = p->classes[c].cell_rows_per_item;
         const int32_t Hc = descs[j].H - 2;
-        for (int32_t cy = 0; cy < p->cells_y; cy += cpi) {
-            const int32_t cy1 = std::min(cy + cpi, p->cells_y);
-            items.push_back({j, (int16_t)cy, (int16_t)cy1, p->classes[c].rows_per_task});
+        const ldp::Geom geo = ldp::make_geom(Hc, descs[j].W - 2, p->gy, p->gx, p->windows);
+        for (int32_t cy = 0; cy < geo.ny; cy += cpi) {
+            const int32_t cy1 = std::min(cy + cpi, geo.ny);
+            items.push_back({j, (uint16_t)cy, (uint16_t)cy1, p->classes[c].rows_per_task});
             const int64_t rows =
-                ldp::cell_start(cy1, Hc, p->cells_y) - ldp::cell_start(cy, Hc, p->cells_y);
+                ldp::geom_row_start(geo, cy1, Hc) - ldp::geom_row_start(geo, cy, Hc);
             size.push_back(rows * (descs[j].W - 2));
         }
     }
-    if ((int64_t)items.size() > p->max_items)
-        return LDP_ERR_NO_MEMORY;
+    if ((int64_t)items.size() > p->max_items) {
+        if (!p->windows)
+            return LDP_ERR_NO_MEMORY;
+        // window plans grow their item table (the graph reads its address
+        // from the meta words, so nothing is re-captured)
+        const int64_t cap = std::max<int64_t>((int64_t)items.size(), p->max_items * 3 / 2);
+        ldp::Item *d = nullptr, *h = nullptr;
+        if (hipMalloc(&d, sizeof(ldp::Item) * cap) != hipSuccess)
+            return LDP_ERR_NO_MEMORY;
+        if (hipHostMalloc(&h, sizeof(ldp::Item) * cap) != hipSuccess) {
+            (void)hipFree(d);
+            return LDP_ERR_NO_MEMORY;
+        }
+        // the old table may still feed a launch in flight
+        if (hipDeviceSynchronize() != hipSuccess) {
+            (void)hipFree(d);
+            (void)hipHostFree(h);
+            return LDP_ERR_HIP;
+        }
+        (void)hipFree(p->d_items);
+        (void)hipHostFree(p->h_items);
+        p->d_items = d;
+        p->h_items = h;
+        p->max_items = cap;
+    }
     std::vector<int64_t> order(items.size());
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(),
@@ -301,14 +403,16 @@ int ldp_batch_plan_set(ldp_batch_plan *p, const ldp_image_desc *descs, int32_t n
         p->h_items[i] = items[order[i]];
     std::copy(descs, descs + n, p->h_descs);
     p->n_items = (int64_t)items.size();
-    p->h_meta[0] = (uint32_t)p->n_items;
-    p->h_meta[1] = 0;
+    p->h_meta->n_items = (uint32_t)p->n_items;
+    p->h_meta->next = 0;
+    p->h_meta->items = p->d_items;
     hipStream_t s = (hipStream_t)stream;
     if (hipMemcpyAsync(p->d_descs, p->h_descs, sizeof(ldp_image_desc) * n, hipMemcpyHostToDevice,
                        s) != hipSuccess ||
         hipMemcpyAsync(p->d_items, p->h_items, sizeof(ldp::Item) * p->n_items,
                        hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(p->d_meta, p->h_meta, 8, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(p->d_meta, p->h_meta, sizeof(ldp::Meta), hipMemcpyHostToDevice, s) !=
+            hipSuccess ||
         hipEventRecord(p->uploaded, s) != hipSuccess)
         return LDP_ERR_HIP;
     return LDP_OK;
@@ -328,8 +432,8 @@ int ldp_batch_run_per_image(ldp_batch_plan *p, ldp_stream_t stream)
     if (!p)
         return LDP_ERR_INVALID_ARG;
     for (const ldp_image_desc &d : p->descs) {
-        int st = ldp::launch_extract(d.img, d.H, d.W, d.stride, p->k, p->flags, p->cells_y, p->cells_x,
-                                     d.codes, d.hist, (hipStream_t)stream);
+        int st = ldp::launch_extract(d.img, d.H, d.W, d.stride, p->k, p->flags, p->gy, p->gx,
+                                     p->windows, d.codes, d.hist, (hipStream_t)stream);
         if (st != LDP_OK)
             return st;
     }

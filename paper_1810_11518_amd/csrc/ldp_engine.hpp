@@ -61,11 +61,58 @@ __host__ __device__ __forceinline__ int32_t cell_start(int32_t c, int32_t n, int
     return (int32_t)(((uint32_t)c * (uint32_t)n + (uint32_t)cells - 1u) / (uint32_t)cells);
 }
 
-// LDS histogram window of a work item: per cell row, cells_x cells of 256
-// uint32 bins followed by one discard cell (pixels that another lane counts).
-__host__ __device__ __forceinline__ uint32_t hist_row_bytes(int32_t cells_x)
+// Histogram cells of a code map: code row r lies in cell row r*ay/by, code
+// column j in cell column j*ax/bx; ny x nx cells.
+//   cells (Eqs. 4-5 over a grid): ay = cells_y, by = Hc, ax = cells_x, bx = Wc;
+//   windows of wy x wx code pixels: ay = ax = 1, by = wy, bx = wx,
+//   ny = ceil(Hc / wy), nx = ceil(Wc / wx) (the last ones cut at the edge).
+// All operands are below 2^16 (window sides are clamped to the map), so the
+// products below are exact in 32 bits.
+struct Geom {
+    uint32_t ay, by, ax, bx;
+    int32_t ny, nx;
+};
+
+__host__ __device__ __forceinline__ Geom make_geom(int32_t Hc, int32_t Wc, int32_t gy, int32_t gx,
+                                                   bool windows)
 {
-    return (uint32_t)(cells_x + 1) * 1024u;
+    Geom g;
+    if (windows) {
+        const int32_t wy = gy < Hc ? gy : Hc, wx = gx < Wc ? gx : Wc;
+        g.ay = g.ax = 1;
+        g.by = (uint32_t)wy;
+        g.bx = (uint32_t)wx;
+        g.ny = (Hc + wy - 1) / wy;
+        g.nx = (Wc + wx - 1) / wx;
+    } else {
+        g.ay = (uint32_t)gy;
+        g.by = (uint32_t)Hc;
+        g.ax = (uint32_t)gx;
+        g.bx = (uint32_t)Wc;
+        g.ny = gy;
+        g.nx = gx;
+    }
+    return g;
+}
+
+// First code row of cell row c (c = ny gives Hc), and first code column of
+// cell column c.
+__host__ __device__ __forceinline__ int32_t geom_row_start(const Geom &g, int32_t c, int32_t Hc)
+{
+    const int32_t r = (int32_t)(((uint32_t)c * g.by + g.ay - 1u) / g.ay);
+    return r < Hc ? r : Hc;
+}
+__host__ __device__ __forceinline__ int32_t geom_col_start(const Geom &g, int32_t c, int32_t Wc)
+{
+    const int32_t j = (int32_t)(((uint32_t)c * g.bx + g.ax - 1u) / g.ax);
+    return j < Wc ? j : Wc;
+}
+
+// LDS histograms of a work item: per cell row, nx cells of 256 uint32 bins
+// followed by one discard cell (pixels that another lane counts).
+__host__ __device__ __forceinline__ uint32_t hist_row_bytes(int32_t nx)
+{
+    return (uint32_t)(nx + 1) * 1024u;
 }
 
 // Loads one image row for the lane: 16 bytes from the 4-aligned offset at or
@@ -93,7 +140,7 @@ __device__ __forceinline__ void unpack_raw(Row &r, const RawRow &rr)
 // Column group of a lane: its first code column (groups of 8, the last one
 // ends at Wc - 1) and the histogram cell column of each pixel, one byte per
 // pixel (bytes 0..3 of cl for pixels 0..3, of ch for 4..7); the discard cell
-// (cells_x) for the leading columns the previous group counts.
+// (nx) for the leading columns the previous group counts.
 struct Cols {
     int32_t j0;
     uint32_t cl, ch;
@@ -101,7 +148,7 @@ struct Cols {
 };
 
 template <bool HIST>
-__device__ __forceinline__ Cols group_cols(const ImgView &im, int32_t cells_x, int32_t g)
+__device__ __forceinline__ Cols group_cols(const ImgView &im, const Geom &geo, int32_t g)
 {
     Cols c;
     c.j0 = min(8 * g, im.Wc - 8);
@@ -111,8 +158,8 @@ __device__ __forceinline__ Cols group_cols(const ImgView &im, int32_t cells_x, i
         const int32_t skip = 8 * g - c.j0;
 #pragma unroll
         for (int p = 0; p < 8; ++p) {
-            const uint32_t cx = ((uint32_t)(c.j0 + p) * (uint32_t)cells_x) / (uint32_t)im.Wc;
-            const uint32_t d = (p < skip ? (uint32_t)cells_x : cx) << (8 * (p & 3));
+            const uint32_t cx = ((uint32_t)(c.j0 + p) * geo.ax) / geo.bx;
+            const uint32_t d = (p < skip ? (uint32_t)geo.nx : cx) << (8 * (p & 3));
             if (p < 4)
                 c.cl |= d;
             else
@@ -235,7 +282,7 @@ __device__ __forceinline__ void run_task(const ImgView &im, uint32_t *lds_bins, 
 // pixels past the map masked (counted in the discard cell).
 template <int K, int MODE, bool HIST, bool CODES>
 __device__ void run_task_narrow(const ImgView &im, uint32_t *lds_bins, uint32_t rowb,
-                                int32_t cells_x, int32_t r0, int32_t r1)
+                                const Geom &geo, int32_t r0, int32_t r1)
 {
     const int nvalid = im.Wc;
     const uint32_t off = im.off0 + (uint32_t)r0 * im.stride;
@@ -253,7 +300,7 @@ __device__ void run_task_narrow(const ImgView &im, uint32_t *lds_bins, uint32_t 
     if constexpr (HIST) {
         for (int p = 0; p < 8; ++p) {
             const uint32_t cx =
-                p < nvalid ? ((uint32_t)p * (uint32_t)cells_x) / (uint32_t)im.Wc : (uint32_t)cells_x;
+                p < nvalid ? ((uint32_t)p * geo.ax) / geo.bx : (uint32_t)geo.nx;
             cb[p] = rowb + cx * 1024u;
         }
     }
@@ -300,32 +347,32 @@ __device__ void run_task_narrow(const ImgView &im, uint32_t *lds_bins, uint32_t 
 // read neighbouring columns), lanes [base, threads) the (q+1)-band groups.
 // Wider maps (more column groups than threads) take whole cell rows per task.
 template <int K, int MODE, bool CODES>
-__device__ __forceinline__ void fused_item(const ImgView &im, uint32_t *lds, int32_t cells_y,
-                                           int32_t cells_x, int32_t cy0, int32_t cy1, int32_t r0,
+__device__ __forceinline__ void fused_item(const ImgView &im, uint32_t *lds, const Geom &geo,
+                                           int32_t cy0, int32_t cy1, int32_t r0,
                                            int32_t r1, uint32_t *hist, bool atomic_flush,
                                            int32_t min_task_rows)
 {
     const int tid = threadIdx.x, nthreads = blockDim.x;
-    const uint32_t row_bytes = hist_row_bytes(cells_x);
-    const int32_t row_words = (cells_x + 1) * 256;
+    const uint32_t row_bytes = hist_row_bytes(geo.nx);
+    const int32_t row_words = (geo.nx + 1) * 256;
     for (int32_t i = tid; i < (cy1 - cy0) * row_words; i += nthreads)
         lds[i] = 0;
     __syncthreads();
     // code rows [a, b) of the current cell row inside [r0, r1)
-    int32_t a = max(r0, cell_start(cy0, im.Hc, cells_y));
-    int32_t b = min(r1, cell_start(cy0 + 1, im.Hc, cells_y));
+    int32_t a = max(r0, geom_row_start(geo, cy0, im.Hc));
+    int32_t b = min(r1, geom_row_start(geo, cy0 + 1, im.Hc));
     if (im.Wc < 8) {
         for (int32_t cy = cy0; cy < cy1; ++cy) {
             if (cy > cy0) {
                 a = b;
-                b = min(r1, cell_start(cy + 1, im.Hc, cells_y));
+                b = min(r1, geom_row_start(geo, cy + 1, im.Hc));
             }
             const int32_t nr = b - a, nsub = min(nthreads, nr);
             if (tid < nsub) {
                 const int32_t a0 = a + (int32_t)(((uint32_t)nr * tid) / (uint32_t)nsub);
                 const int32_t a1 = a + (int32_t)(((uint32_t)nr * (tid + 1)) / (uint32_t)nsub);
                 if (a1 > a0)
-                    run_task_narrow<K, MODE, true, CODES>(im, lds, (cy - cy0) * row_bytes, cells_x,
+                    run_task_narrow<K, MODE, true, CODES>(im, lds, (cy - cy0) * row_bytes, geo,
                                                     a0, a1);
             }
         }
@@ -349,11 +396,11 @@ __device__ __forceinline__ void fused_item(const ImgView &im, uint32_t *lds, int
                     sb = (uint32_t)(tid - base) / (uint32_t)nx;
                     nb = (uint32_t)nsub + 1;
                 }
-                const Cols c = group_cols<true>(im, cells_x, (int32_t)g);
+                const Cols c = group_cols<true>(im, geo, (int32_t)g);
                 for (int32_t cy = cy0; cy < cy1; ++cy) {
                     if (cy > cy0) {
                         a = b;
-                        b = min(r1, cell_start(cy + 1, im.Hc, cells_y));
+                        b = min(r1, geom_row_start(geo, cy + 1, im.Hc));
                     }
                     // 32-bit arithmetic: nr * nb <= 2^16 * 2^10
                     const uint32_t nr = (uint32_t)max(b - a, 0);
@@ -367,19 +414,19 @@ __device__ __forceinline__ void fused_item(const ImgView &im, uint32_t *lds, int
             for (int32_t cy = cy0; cy < cy1; ++cy) {
                 if (cy > cy0) {
                     a = b;
-                    b = min(r1, cell_start(cy + 1, im.Hc, cells_y));
+                    b = min(r1, geom_row_start(geo, cy + 1, im.Hc));
                 }
                 for (int32_t g = tid; g < ngroups; g += nthreads)
                     run_task<K, MODE, true, CODES>(im, lds, (cy - cy0) * row_bytes,
-                                             group_cols<true>(im, cells_x, g), a, b);
+                                             group_cols<true>(im, geo, g), a, b);
             }
         }
     }
     __syncthreads();
     for (int32_t r = 0; r < cy1 - cy0; ++r) {
         const uint32_t *src = lds + r * row_words;
-        uint32_t *dst = hist + (int64_t)(cy0 + r) * cells_x * 256;
-        for (int32_t i = tid; i < cells_x * 256; i += nthreads) {
+        uint32_t *dst = hist + (int64_t)(cy0 + r) * geo.nx * 256;
+        for (int32_t i = tid; i < geo.nx * 256; i += nthreads) {
             const uint32_t v = src[i];
             if (!atomic_flush)
                 dst[i] = v;

@@ -49,10 +49,12 @@ constexpr int32_t kMaxFusedCellsX = 63;
 
 int launch_codes(const uint8_t *img, int32_t H, int32_t W, int64_t stride, int32_t k,
                  int32_t flags, uint8_t *codes, hipStream_t s);
-int launch_histograms(const uint8_t *codes, int32_t H, int32_t W, int32_t cells_y,
-                      int32_t cells_x, uint32_t *hist, hipStream_t s);
+// (gy, gx) are the cell counts (cells_y, cells_x), or with `windows` the
+// window sides in code pixels.
+int launch_histograms(const uint8_t *codes, int32_t H, int32_t W, int32_t gy, int32_t gx,
+                      bool windows, uint32_t *hist, hipStream_t s);
 int launch_extract(const uint8_t *img, int32_t H, int32_t W, int64_t stride, int32_t k,
-                   int32_t flags, int32_t cells_y, int32_t cells_x, uint8_t *codes,
+                   int32_t flags, int32_t gy, int32_t gx, bool windows, uint8_t *codes,
                    uint32_t *hist, hipStream_t s);
 
 }  // namespace ldp

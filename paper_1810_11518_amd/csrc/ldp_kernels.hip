@@ -35,10 +35,11 @@ __global__ void __launch_bounds__(256) LDP_CODES_ATTR codes_kernel(const uint8_t
     const int32_t band = task / ngroups;
     const int32_t r0 = band * band_rows;
     const int32_t r1 = min(r0 + band_rows, im.Hc);
+    const Geom none{1, 1, 1, 1, 1, 1};  // no histograms here
     if (im.Wc < 8)
-        run_task_narrow<K, MODE, false, true>(im, nullptr, 0, 0, r0, r1);
+        run_task_narrow<K, MODE, false, true>(im, nullptr, 0, none, r0, r1);
     else
-        run_task<K, MODE, false, true>(im, nullptr, 0, group_cols<false>(im, 0, g), r0, r1);
+        run_task<K, MODE, false, true>(im, nullptr, 0, group_cols<false>(im, none, g), r0, r1);
 }
 
 // ---------------------------------------------------------------- histograms
@@ -46,7 +47,7 @@ __global__ void __launch_bounds__(256) LDP_CODES_ATTR codes_kernel(const uint8_t
 // `nsplit` parts.  Wave-private LDS bins; one store (or atomic add when the
 // cell is split) per bin.
 __global__ void __launch_bounds__(256) hist_kernel(const uint8_t *__restrict__ codes, int32_t Hc,
-                                                   int32_t Wc, int32_t cells_y, int32_t cells_x,
+                                                   int32_t Wc, Geom geo,
                                                    uint32_t *__restrict__ hist, int32_t nsplit)
 {
     __shared__ uint32_t bins[4][256];
@@ -56,8 +57,8 @@ __global__ void __launch_bounds__(256) hist_kernel(const uint8_t *__restrict__ c
         bins[w][tid] = 0;
     __syncthreads();
     const int32_t cx = blockIdx.x, cy = blockIdx.y, sp = blockIdx.z;
-    const int32_t ry0 = cell_start(cy, Hc, cells_y), ry1 = cell_start(cy + 1, Hc, cells_y);
-    const int32_t c0 = cell_start(cx, Wc, cells_x), c1 = cell_start(cx + 1, Wc, cells_x);
+    const int32_t ry0 = geom_row_start(geo, cy, Hc), ry1 = geom_row_start(geo, cy + 1, Hc);
+    const int32_t c0 = geom_col_start(geo, cx, Wc), c1 = geom_col_start(geo, cx + 1, Wc);
     const int32_t nrows = ry1 - ry0, width = c1 - c0;
     const int32_t a0 = ry0 + (int32_t)((int64_t)nrows * sp / nsplit);
     const int32_t a1 = ry0 + (int32_t)((int64_t)nrows * (sp + 1) / nsplit);
@@ -69,7 +70,7 @@ __global__ void __launch_bounds__(256) hist_kernel(const uint8_t *__restrict__ c
     }
     __syncthreads();
     uint32_t total = bins[0][tid] + bins[1][tid] + bins[2][tid] + bins[3][tid];
-    uint32_t *dst = hist + ((int64_t)cy * cells_x + cx) * 256 + tid;
+    uint32_t *dst = hist + ((int64_t)cy * geo.nx + cx) * 256 + tid;
     if (nsplit == 1)
         *dst = total;
     else if (total)
@@ -87,17 +88,16 @@ __global__ void zero_kernel(uint32_t *__restrict__ p, int64_t n)
 template <int K, int MODE, bool CODES>
 __global__ void __launch_bounds__(1024) fused_kernel(const uint8_t *__restrict__ img,
                                                      int64_t stride, int32_t H, int32_t W,
-                                                     uint8_t *codes, uint32_t *hist,
-                                                     int32_t cells_y, int32_t cells_x,
+                                                     uint8_t *codes, uint32_t *hist, Geom geo,
                                                      int32_t split)
 {
     extern __shared__ uint32_t lds[];
     const ImgView im = make_view(img, stride, H, W, codes);
     const int32_t cy = blockIdx.x / split, sp = blockIdx.x % split;
-    const int32_t ry0 = cell_start(cy, im.Hc, cells_y), ry1 = cell_start(cy + 1, im.Hc, cells_y);
+    const int32_t ry0 = geom_row_start(geo, cy, im.Hc), ry1 = geom_row_start(geo, cy + 1, im.Hc);
     const int32_t r0 = ry0 + (int32_t)((int64_t)(ry1 - ry0) * sp / split);
     const int32_t r1 = ry0 + (int32_t)((int64_t)(ry1 - ry0) * (sp + 1) / split);
-    fused_item<K, MODE, CODES>(im, lds, cells_y, cells_x, cy, cy + 1, r0, r1, hist, split > 1, 4);
+    fused_item<K, MODE, CODES>(im, lds, geo, cy, cy + 1, r0, r1, hist, split > 1, 4);
 }
 
 // ---------------------------------------------------------------- dispatch
@@ -144,10 +144,10 @@ template <int K, int MODE, bool CODES>
 struct FusedLaunch {
     static hipError_t launch(dim3 grid, dim3 block, size_t lds, hipStream_t s, const uint8_t *img,
                              int64_t stride, int32_t H, int32_t W, uint8_t *codes,
-                             uint32_t *hist, int32_t cells_y, int32_t cells_x, int32_t split)
+                             uint32_t *hist, Geom geo, int32_t split)
     {
         hipLaunchKernelGGL((fused_kernel<K, MODE, CODES>), grid, block, lds, s, img, stride, H, W,
-                           codes, hist, cells_y, cells_x, split);
+                           codes, hist, geo, split);
         return hipGetLastError();
     }
 };
@@ -168,58 +168,60 @@ int launch_codes(const uint8_t *img, int32_t H, int32_t W, int64_t stride, int32
     return e == hipSuccess ? LDP_OK : LDP_ERR_HIP;
 }
 
-int launch_histograms(const uint8_t *codes, int32_t H, int32_t W, int32_t cells_y,
-                      int32_t cells_x, uint32_t *hist, hipStream_t s)
+int launch_histograms(const uint8_t *codes, int32_t H, int32_t W, int32_t gy, int32_t gx,
+                      bool windows, uint32_t *hist, hipStream_t s)
 {
     const int32_t Hc = H - 2, Wc = W - 2;
-    const int64_t cells = (int64_t)cells_y * cells_x;
+    const Geom geo = make_geom(Hc, Wc, gy, gx, windows);
+    const int64_t cells = (int64_t)geo.ny * geo.nx;
     const int64_t per_cell = (int64_t)Hc * Wc / cells;
     // split cells so that there are enough workgroups and none is huge
     int32_t nsplit = 1;
     while (nsplit < 64 && (cells * nsplit < 512 || per_cell / nsplit > (1 << 16)) &&
-           (Hc / cells_y) / (nsplit * 2) >= 1)
+           (Hc / geo.ny) / (nsplit * 2) >= 1)
         nsplit *= 2;
     if (nsplit > 1) {
         int64_t n = cells * 256;
         hipLaunchKernelGGL(zero_kernel, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 1024)),
                            dim3(256), 0, s, hist, n);
     }
-    hipLaunchKernelGGL(hist_kernel, dim3(cells_x, cells_y, nsplit), dim3(256), 0, s, codes, Hc,
-                       Wc, cells_y, cells_x, hist, nsplit);
+    hipLaunchKernelGGL(hist_kernel, dim3(geo.nx, geo.ny, nsplit), dim3(256), 0, s, codes, Hc, Wc,
+                       geo, hist, nsplit);
     return hipGetLastError() == hipSuccess ? LDP_OK : LDP_ERR_HIP;
 }
 
 // LDS bytes of one cell row of histograms plus its discard cell
-static size_t fused_lds_bytes(int32_t cells_x) { return hist_row_bytes(cells_x); }
+static size_t fused_lds_bytes(int32_t nx) { return hist_row_bytes(nx); }
 
 int launch_extract(const uint8_t *img, int32_t H, int32_t W, int64_t stride, int32_t k,
-                   int32_t flags, int32_t cells_y, int32_t cells_x, uint8_t *codes,
+                   int32_t flags, int32_t gy, int32_t gx, bool windows, uint8_t *codes,
                    uint32_t *hist, hipStream_t s)
 {
     const int32_t Hc = H - 2, Wc = W - 2;
-    if (cells_x > kMaxFusedCellsX) {
+    const Geom geo = make_geom(Hc, Wc, gy, gx, windows);
+    if (geo.nx > kMaxFusedCellsX) {
         // one cell row of histograms does not fit in LDS: two passes
         if (!codes)
             return LDP_ERR_UNSUPPORTED;
         int st = launch_codes(img, H, W, stride, k, flags, codes, s);
-        return st != LDP_OK ? st : launch_histograms(codes, H, W, cells_y, cells_x, hist, s);
+        return st != LDP_OK ? st : launch_histograms(codes, H, W, gy, gx, windows, hist, s);
     }
     const int32_t ngroups = (Wc + 7) / 8;
     int threads = ngroups >= 768 ? 1024 : ngroups >= 384 ? 512 : 256;
     // enough workgroups to fill the device: split cell rows
     int32_t split = 1;
-    const int32_t rows_per_cell = Hc / cells_y;
-    while ((int64_t)cells_y * split < 512 && rows_per_cell / (split * 2) >= 8 && split < 64)
+    const int32_t rows_per_cell = Hc / geo.ny;
+    while ((int64_t)geo.ny * split < 512 && rows_per_cell / (split * 2) >= 8 && split < 64)
         split *= 2;
     if (split > 1) {
-        int64_t n = (int64_t)cells_y * cells_x * 256;
+        int64_t n = (int64_t)geo.ny * geo.nx * 256;
         hipLaunchKernelGGL(zero_kernel, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 1024)),
                            dim3(256), 0, s, hist, n);
     }
-    size_t lds = fused_lds_bytes(cells_x);
+    size_t lds = fused_lds_bytes(geo.nx);
     hipError_t e = dispatch<FusedLaunch>(k, rank_mode(flags), codes != nullptr,
-                                         dim3(cells_y * split), dim3(threads), lds, s, img,
-                                         stride, H, W, codes, hist, cells_y, cells_x, split);
+                                         dim3(geo.ny * split), dim3(threads), lds, s, img,
+                                         stride, H, W, codes, hist, geo, split);
     return e == hipSuccess ? LDP_OK : LDP_ERR_HIP;
 }
 
@@ -253,7 +255,7 @@ int ldp_histograms(const uint8_t *codes, int32_t H, int32_t W, int32_t cells_y,
     int st = ldp::check_cells(H, W, cells_y, cells_x);
     if (st != LDP_OK)
         return st;
-    return ldp::launch_histograms(codes, H, W, cells_y, cells_x, hist, (hipStream_t)stream);
+    return ldp::launch_histograms(codes, H, W, cells_y, cells_x, false, hist, (hipStream_t)stream);
 }
 
 int ldp_extract_ex(const uint8_t *img, int32_t H, int32_t W, int64_t stride, int32_t k,
@@ -268,7 +270,7 @@ int ldp_extract_ex(const uint8_t *img, int32_t H, int32_t W, int64_t stride, int
     st = ldp::check_cells(H, W, cells_y, cells_x);
     if (st != LDP_OK)
         return st;
-    return ldp::launch_extract(img, H, W, stride, k, flags, cells_y, cells_x, codes, hist,
+    return ldp::launch_extract(img, H, W, stride, k, flags, cells_y, cells_x, false, codes, hist,
                                (hipStream_t)stream);
 }
 
@@ -277,6 +279,41 @@ int ldp_extract(const uint8_t *img, int32_t H, int32_t W, int64_t stride, int32_
                 ldp_stream_t stream)
 {
     return ldp_extract_ex(img, H, W, stride, k, 0, cells_y, cells_x, codes, hist, stream);
+}
+
+int ldp_window_grid(int32_t H, int32_t W, int32_t win_y, int32_t win_x, int32_t *ny,
+                    int32_t *nx)
+{
+    if (H < 3 || W < 3 || H > LDP_MAX_SIDE || W > LDP_MAX_SIDE || win_y < 1 || win_x < 1)
+        return LDP_ERR_INVALID_ARG;
+    const ldp::Geom geo = ldp::make_geom(H - 2, W - 2, win_y, win_x, true);
+    if (ny)
+        *ny = geo.ny;
+    if (nx)
+        *nx = geo.nx;
+    return LDP_OK;
+}
+
+int ldp_histograms_windows(const uint8_t *codes, int32_t H, int32_t W, int32_t win_y,
+                           int32_t win_x, uint32_t *hist, ldp_stream_t stream)
+{
+    if (!codes || !hist || H < 3 || W < 3 || H > LDP_MAX_SIDE || W > LDP_MAX_SIDE || win_y < 1 ||
+        win_x < 1)
+        return LDP_ERR_INVALID_ARG;
+    return ldp::launch_histograms(codes, H, W, win_y, win_x, true, hist, (hipStream_t)stream);
+}
+
+int ldp_extract_windows(const uint8_t *img, int32_t H, int32_t W, int64_t stride, int32_t k,
+                        int32_t flags, int32_t win_y, int32_t win_x, uint8_t *codes,
+                        uint32_t *hist, ldp_stream_t stream)
+{
+    int st = ldp::check_image(img, H, W, stride);
+    if (st != LDP_OK)
+        return st;
+    if (!hist || k < 1 || k > 8 || !ldp::flags_ok(flags) || win_y < 1 || win_x < 1)
+        return LDP_ERR_INVALID_ARG;
+    return ldp::launch_extract(img, H, W, stride, k, flags, win_y, win_x, true, codes, hist,
+                               (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -76,6 +76,13 @@ def test_invalid_arguments_return_before_any_launch(lib):
     assert lib.ldp_compact_histograms(p, -1, 3, p, None) == E
     assert lib.ldp_compact_histograms(None, 5, 3, p, None) == E
     assert lib.ldp_compact_histograms(None, 0, 3, None, None) == binding.LDP_OK  # nothing to do
+    assert lib.ldp_extract_windows(p, 10, 10, 10, 3, 0, 0, 2, p, p, None) == E
+    assert lib.ldp_extract_windows(p, 10, 10, 10, 3, 0, 2, 0, p, p, None) == E
+    assert lib.ldp_extract_windows(p, 10, 10, 10, 3, 8, 2, 2, p, p, None) == E
+    assert lib.ldp_histograms_windows(p, 10, 10, 0, 1, p, None) == E
+    assert lib.ldp_batch_plan_create_windows(ctypes.byref(plan), 10, 100, 2, 3, 0, 5, 5, None) == E
+    assert (lib.ldp_batch_plan_create_windows(ctypes.byref(plan), 10, 10 ** 6, 1000, 3, 0, 5, 5,
+                                              None) == binding.LDP_ERR_UNSUPPORTED)  # 200 windows
     srv = ctypes.c_void_p()
     bad = binding.ServerConfig(0, 1, 1, 1, 3, 7, 6, 1, 0)
     assert lib.ldp_server_create(ctypes.byref(srv), ctypes.byref(bad)) == E
@@ -90,6 +97,15 @@ def test_compact_bin_counts(lib):
         assert lib.ldp_compact_bins(k) == math.comb(8, k) + 1
     assert lib.ldp_compact_bins(0) == binding.LDP_ERR_INVALID_ARG
     assert lib.ldp_compact_bins(9) == binding.LDP_ERR_INVALID_ARG
+
+
+def test_window_grid_counts_of_table3(lib):
+    """Table 3: 784, 196, 144, 36 and 9 windows for a 280x280 image."""
+    for w, n in ((10, 784), (20, 196), (25, 144), (50, 36), (100, 9)):
+        ny, nx = binding.window_grid(280, 280, w, w)
+        assert ny * nx == n
+    assert binding.window_grid(3, 3, 5, 5) == (1, 1)
+    assert lib.ldp_window_grid(2, 9, 1, 1, None, None) == binding.LDP_ERR_INVALID_ARG
 
 
 def test_tune_struct_layout():

@@ -37,8 +37,9 @@ def _blocks(body):
 def main_loop_valu(asm, k, mode):
     """VALU instructions of the first innermost loop of batch_kernel<k, mode>
     that holds 24 LDS instructions (the x3-unrolled row loop: 8 per row step)."""
-    name = "_ZN3ldp12batch_kernelILi%dELi%dEEEvPK14ldp_image_descPKNS_4ItemEPjii" % (k, mode)
-    i = asm.index(name + ":")
+    m = re.search(r"^(_ZN3ldp12batch_kernelILi%dELi%dEEEv\w*):" % (k, mode), asm, re.M)
+    assert m, "batch_kernel<%d, %d> not found" % (k, mode)
+    i = m.start()
     body = asm[i:asm.index(".Lfunc_end", i)]
     blocks = _blocks(body)
     for lab, com, _ in blocks:
