@@ -190,7 +190,9 @@ def variant_bench(binding, torch, args, plan_args, descs, hist, codes, code_off,
              "correlation (flags LDP_DIRECT_MASKS): the unaccelerated route"),
             ("lbp", binding.LDP_CODE_LBP, VALU_PER_ROW_STEP_LBP,
              "LBP labels and histograms of the same batch (flags LDP_CODE_LBP)")):
-        plan = binding.BatchPlan(n, pixels, k, cells[0], cells[1], tune, flags=flag)
+        from paper_1810_11518_amd import autotune
+        vtune = autotune.lookup(Hs, Ws, k, cells, flags=flag) or tune
+        plan = binding.BatchPlan(n, pixels, k, cells[0], cells[1], vtune, flags=flag)
         plan.set(descs)
         ms = _timed(torch, plan.run, args.variant_steps)
         plan.close()
@@ -199,7 +201,7 @@ def variant_bench(binding, torch, args, plan_args, descs, hist, codes, code_off,
         lane_ops = per_step / 8.0 * code_pixels
         out[name] = {
             "what": what, "value": round(pixels / (ms * 1e-3) / 1e6, 1), "unit": "Mpixel/s",
-            "ms": round(ms, 4), "vs_signed": round(ms / ms_signed, 3),
+            "ms": round(ms, 4), "vs_signed": round(ms / ms_signed, 3), "tune": vtune,
             "roofline": {"bound": "alu", "unit": "T VALU lane-instr/s",
                          "achieved": round(lane_ops / (ms * 1e-3) / 1e12, 2),
                          "peak": round(VALU_PEAK_T, 2),

@@ -207,8 +207,9 @@ typedef struct ldp_image_desc {
 #define LDP_MAX_SIZE_CLASSES 4
 typedef struct ldp_size_class {
     int64_t max_pixels;         /* upper bound of H*W for the class */
-    int32_t cell_rows_per_item; /* cell rows of one image per work item, >= 1 (at most
-                                   65536 / ((cells_x + 1) * 1024): its histograms sit in LDS) */
+    int32_t cell_rows_per_item; /* cell rows of one image per work item, >= 1; lowered so
+                                   that an item's histograms ((cells_x + 1) KiB per cell row,
+                                   in LDS) take at most 32 KiB, or one cell row */
     int32_t rows_per_task;      /* target code rows per lane task, >= 1 */
 } ldp_size_class;
 

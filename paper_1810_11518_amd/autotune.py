@@ -46,8 +46,12 @@ def size_signature(Hs, Ws):
     return "mix:%d/%d/%d" % tuple(q)
 
 
-def key(Hs, Ws, k, cells):
-    return "%s|k%d|%dx%d|%s" % (arch(), k, cells[0], cells[1], size_signature(Hs, Ws))
+def key(Hs, Ws, k, cells, flags=0):
+    """Cache key: architecture, k, cell grid, size signature, and the
+    ldp_*_ex flags when set (the variants weigh arithmetic against memory
+    traffic differently, so their best split differs)."""
+    base = "%s|k%d|%dx%d|%s" % (arch(), k, cells[0], cells[1], size_signature(Hs, Ws))
+    return base if not flags else base + "|f%d" % flags
 
 
 def load_cache(path=CACHE):
@@ -57,9 +61,9 @@ def load_cache(path=CACHE):
     return {}
 
 
-def lookup(Hs, Ws, k, cells, path=CACHE):
-    """Cached tune dict for this batch shape, or None."""
-    return load_cache(path).get(key(Hs, Ws, k, cells), {}).get("tune")
+def lookup(Hs, Ws, k, cells, path=CACHE, flags=0):
+    """Cached tune dict for this batch shape (and flags), or None."""
+    return load_cache(path).get(key(Hs, Ws, k, cells, flags), {}).get("tune")
 
 
 def default_classes(Hs, Ws, cells_y):
@@ -74,10 +78,10 @@ def default_classes(Hs, Ws, cells_y):
             dict(cell_rows_per_item=1, rows_per_task=8)]
 
 
-def _time_plan(binding, descs, n, pixels, k, cells, tune, reps=8, rounds=3):
+def _time_plan(binding, descs, n, pixels, k, cells, tune, reps=8, rounds=3, flags=0):
     """Best mean launch time (ms) over `rounds` rounds of `reps` launches."""
     import torch
-    plan = binding.BatchPlan(n, pixels, k, cells[0], cells[1], tune)
+    plan = binding.BatchPlan(n, pixels, k, cells[0], cells[1], tune, flags=flags)
     try:
         plan.set(descs)
         for _ in range(2):
@@ -98,10 +102,10 @@ def _time_plan(binding, descs, n, pixels, k, cells, tune, reps=8, rounds=3):
         plan.close()
 
 
-def _warm_up(binding, descs, n, pixels, k, cells, tune, seconds=0.3):
+def _warm_up(binding, descs, n, pixels, k, cells, tune, seconds=0.3, flags=0):
     """Keep the device busy with this batch for about `seconds`."""
     import torch
-    plan = binding.BatchPlan(n, pixels, k, cells[0], cells[1], tune)
+    plan = binding.BatchPlan(n, pixels, k, cells[0], cells[1], tune, flags=flags)
     try:
         plan.set(descs)
         t_end = time.time() + seconds
@@ -113,16 +117,17 @@ def _warm_up(binding, descs, n, pixels, k, cells, tune, seconds=0.3):
         plan.close()
 
 
-def tune_batch(descs, Hs, Ws, k, cells, budget_s=60.0, verbose=False):
+def tune_batch(descs, Hs, Ws, k, cells, budget_s=60.0, verbose=False, flags=0):
     """Coordinate descent over ldp_tune for the device-resident batch `descs`
-    (a ctypes ImageDesc array).  Returns (best tune dict, best ms)."""
+    (a ctypes ImageDesc array) and ldp_*_ex `flags`.  Returns (best tune
+    dict, best ms)."""
     from . import binding
     n = len(descs)
     pixels = int((np.asarray(Hs, dtype=np.int64) * np.asarray(Ws, dtype=np.int64)).sum())
     t_end = time.time() + budget_s
     best = dict(block_threads=256, classes=default_classes(Hs, Ws, cells[0]))
-    _warm_up(binding, descs, n, pixels, k, cells, best)
-    best_ms = _time_plan(binding, descs, n, pixels, k, cells, best)
+    _warm_up(binding, descs, n, pixels, k, cells, best, flags=flags)
+    best_ms = _time_plan(binding, descs, n, pixels, k, cells, best, flags=flags)
     seen = {json.dumps(best, sort_keys=True): best_ms}
 
     def attempt(cand):
@@ -131,7 +136,7 @@ def tune_batch(descs, Hs, Ws, k, cells, budget_s=60.0, verbose=False):
         if s in seen or time.time() > t_end:
             return
         try:
-            ms = _time_plan(binding, descs, n, pixels, k, cells, cand)
+            ms = _time_plan(binding, descs, n, pixels, k, cells, cand, flags=flags)
         except binding.LdpError:
             return
         seen[s] = ms
@@ -159,7 +164,7 @@ def tune_batch(descs, Hs, Ws, k, cells, budget_s=60.0, verbose=False):
     again = {s: float("inf") for s, _ in lead}
     for _ in range(3):
         for s in again:
-            ms = _time_plan(binding, descs, n, pixels, k, cells, json.loads(s))
+            ms = _time_plan(binding, descs, n, pixels, k, cells, json.loads(s), flags=flags)
             again[s] = min(again[s], ms)
     s_best = min(again, key=again.get)
     if verbose:
@@ -168,9 +173,9 @@ def tune_batch(descs, Hs, Ws, k, cells, budget_s=60.0, verbose=False):
     return json.loads(s_best), again[s_best]
 
 
-def save(Hs, Ws, k, cells, tune, ms, path=CACHE, note=""):
+def save(Hs, Ws, k, cells, tune, ms, path=CACHE, note="", flags=0):
     cache = load_cache(path)
-    cache[key(Hs, Ws, k, cells)] = {"tune": tune, "ms": round(ms, 4), "note": note}
+    cache[key(Hs, Ws, k, cells, flags)] = {"tune": tune, "ms": round(ms, 4), "note": note}
     tmp = path + ".tmp%d" % os.getpid()
     with open(tmp, "w") as f:
         json.dump(cache, f, indent=1, sort_keys=True)

@@ -217,8 +217,10 @@ int create_plan(ldp_batch_plan **out, int32_t max_images, int64_t max_pixels, in
         return LDP_ERR_INVALID_ARG;
     }
     // an item's cell rows of histograms must fit in 64 KB of LDS (nx_max <= 63
-    // leaves room for at least one)
-    const int32_t lds_cpi = (int32_t)(65536u / ldp::hist_row_bytes(nx_max));
+    // leaves room for at least one), and take at most 32 KB when one row
+    // allows it: five 256-thread workgroups per CU (160 KB of LDS), the
+    // occupancy the kernel is built for
+    const int32_t lds_cpi = std::max<int32_t>(1, (int32_t)(32768u / ldp::hist_row_bytes(nx_max)));
     int32_t max_cpi = 1, min_cpi = windows ? 65535 : gy;
     for (int c = 0; c < p->n_classes; ++c) {
         ldp_size_class &sc = p->classes[c];
