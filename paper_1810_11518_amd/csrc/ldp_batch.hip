@@ -53,12 +53,15 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v)
 // (gy, gx): cells_y x cells_x cells, or with `windows` window sides in code
 // pixels (every image's cell grid follows from its own size).
 template <int K, int MODE>
+// The item number is broadcast through the LDS word after the histograms
+// (`item_slot`, in words): with no static LDS the histograms start at LDS
+// address 0, so a bin address needs no base added.
 __global__ void __launch_bounds__(1024) LDP_BATCH_ATTR batch_kernel(const ldp_image_desc *__restrict__ descs,
                                                      Meta *meta, int32_t gy, int32_t gx,
-                                                     int32_t windows)
+                                                     int32_t windows, int32_t item_slot)
 {
     extern __shared__ uint32_t lds[];
-    __shared__ uint32_t s_item;
+    uint32_t &s_item = lds[item_slot];
     // the item count and table address are the same for every lane:
     // readfirstlane keeps them (and what is read through them) in scalar
     // registers, which the buffer descriptors built from them must be in
@@ -93,7 +96,7 @@ __global__ void __launch_bounds__(1024) LDP_BATCH_ATTR batch_kernel(const ldp_im
     }
 }
 
-typedef void (*batch_fn)(const ldp_image_desc *, Meta *, int32_t, int32_t, int32_t);
+typedef void (*batch_fn)(const ldp_image_desc *, Meta *, int32_t, int32_t, int32_t, int32_t);
 
 template <int MODE>
 static batch_fn batch_kernel_for_mode(int k)
@@ -238,8 +241,10 @@ int create_plan(ldp_batch_plan **out, int32_t max_images, int64_t max_pixels, in
     // item table: enough for max_images images of a cell grid; window plans
     // start at 8 items per image and grow when a batch needs more
     p->max_items = (int64_t)max_images * (windows ? 8 : (gy + min_cpi - 1) / min_cpi);
-    // LDS: the largest item's cell rows, each with its discard cell
-    p->lds_bytes = (size_t)max_cpi * ldp::hist_row_bytes(nx_max);
+    // LDS: the largest item's cell rows, each with its discard cell, then the
+    // item broadcast word (16 bytes keep the allocation aligned)
+    const size_t hist_bytes = (size_t)max_cpi * ldp::hist_row_bytes(nx_max);
+    p->lds_bytes = hist_bytes + 16;
     if (hipGetDevice(&p->device) != hipSuccess) {
         delete p;
         return LDP_ERR_HIP;
@@ -276,7 +281,8 @@ int create_plan(ldp_batch_plan **out, int32_t max_images, int64_t max_pixels, in
         return fail(LDP_ERR_HIP);
     hipLaunchKernelGGL(ldp::clear_counter_kernel, dim3(1), dim3(1), 0, p->cap_stream, p->d_meta);
     hipLaunchKernelGGL(fn, dim3(p->grid), dim3(p->threads), p->lds_bytes, p->cap_stream,
-                       (const ldp_image_desc *)p->d_descs, p->d_meta, gy, gx, windows ? 1 : 0);
+                       (const ldp_image_desc *)p->d_descs, p->d_meta, gy, gx, windows ? 1 : 0,
+                       (int32_t)(hist_bytes / 4));
     hipError_t ce = hipStreamEndCapture(p->cap_stream, &p->graph);
     if (ce != hipSuccess || hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) !=
                                 hipSuccess)

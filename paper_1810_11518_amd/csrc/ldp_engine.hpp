@@ -174,18 +174,18 @@ __device__ __forceinline__ Cols group_cols(const ImgView &im, const Geom &geo, i
 struct Walk {
     uint32_t off, last_off;  // image byte offset of the prefetched / last row
     uint32_t coff;           // code byte offset of the current code row
-    uint32_t rowb;           // LDS byte offset of the cell row's histograms
-    uint32_t cl, ch;         // per-pixel cell columns (Cols)
+    uint32_t cl, ch;         // per-pixel LDS cell index: cell row * (nx + 1) + cell column
     bool uniform_cell;
 };
 
-// LDS byte address of the bin of pixel q (0..3) of the code word x whose
-// cell bytes are d: ((cell << 8) | code) * 4 past the cell row.
-__device__ __forceinline__ uint32_t bin_addr(uint32_t x, uint32_t d, int q, uint32_t rowb)
+// LDS byte address of the bin of pixel q (0..3) of the code word x whose LDS
+// cell indices are the bytes of d: ((cell << 8) | code) * 4.  An item's LDS
+// holds at most 64 cells, so every cell index fits its byte.
+__device__ __forceinline__ uint32_t bin_addr(uint32_t x, uint32_t d, int q)
 {
     // byte 0 = code byte q of x, byte 1 = cell byte q of d, bytes 2, 3 = 0
     const uint32_t sel = (uint32_t)q | ((uint32_t)(4 + q) << 8) | 0x0C0C0000u;
-    return (__builtin_amdgcn_perm(d, x, sel) << 2) + rowb;
+    return __builtin_amdgcn_perm(d, x, sel) << 2;
 }
 
 // Image rows loaded ahead of use: one for the LDP modes (their arithmetic
@@ -228,12 +228,11 @@ __device__ __forceinline__ void step(const ImgView &im, uint32_t *lds_bins, Walk
         char *lds = reinterpret_cast<char *>(lds_bins);
         if (w.uniform_cell && lo == hi && lo == __builtin_amdgcn_alignbyte(lo, lo, 1)) {
             // eight equal codes in one cell (flat regions): one update
-            atomicAdd(reinterpret_cast<uint32_t *>(lds + bin_addr(lo, w.cl, 0, w.rowb)), 8u);
+            atomicAdd(reinterpret_cast<uint32_t *>(lds + bin_addr(lo, w.cl, 0)), 8u);
         } else {
 #pragma unroll
             for (int p = 0; p < 8; ++p) {
-                const uint32_t addr = p < 4 ? bin_addr(lo, w.cl, p, w.rowb)
-                                            : bin_addr(hi, w.ch, p - 4, w.rowb);
+                const uint32_t addr = p < 4 ? bin_addr(lo, w.cl, p) : bin_addr(hi, w.ch, p - 4);
                 atomicAdd(reinterpret_cast<uint32_t *>(lds + addr), 1u);
             }
         }
@@ -250,9 +249,10 @@ __device__ __forceinline__ void run_task(const ImgView &im, uint32_t *lds_bins, 
     w.off = im.off0 + (uint32_t)r0 * im.stride + (uint32_t)c.j0;
     w.last_off = im.off0 + (uint32_t)(im.H - 1) * im.stride + (uint32_t)c.j0;
     w.coff = (uint32_t)r0 * (uint32_t)im.Wc + (uint32_t)c.j0;
-    w.rowb = rowb;
-    w.cl = c.cl;
-    w.ch = c.ch;
+    // the cell row's first LDS cell, added to every pixel's byte
+    const uint32_t row_cells = (rowb >> 10) * 0x01010101u;
+    w.cl = c.cl + row_cells;
+    w.ch = c.ch + row_cells;
     w.uniform_cell = c.uniform_cell;
     RawRow raw, raw2;
     Row A, B, C;
