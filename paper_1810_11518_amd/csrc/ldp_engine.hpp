@@ -188,31 +188,16 @@ __device__ __forceinline__ uint32_t bin_addr(uint32_t x, uint32_t d, int q)
     return __builtin_amdgcn_perm(d, x, sel) << 2;
 }
 
-// Image rows loaded ahead of use: one for the LDP modes (their arithmetic
-// per row covers a load), two for LBP, whose few instructions per row do not.
-template <int MODE>
-__device__ __forceinline__ constexpr int prefetch_rows()
-{
-    return MODE == CODE_LBP ? 2 : 1;
-}
-
 // One code row: the next image row arrives in `raw` and becomes `b`; t and m
 // are the two rows above; Vt = X_t + X_m.  Writes Vb = X_m + X_b.
 template <int K, int MODE, bool HIST, bool CODES>
 __device__ __forceinline__ void step(const ImgView &im, uint32_t *lds_bins, Walk &w, RawRow &raw,
-                                     RawRow &raw2, const Row &t, const Row &m, Row &b,
-                                     const uint32_t (&Vt)[6], uint32_t (&Vb)[6])
+                                     const Row &t, const Row &m, Row &b, const uint32_t (&Vt)[6],
+                                     uint32_t (&Vb)[6])
 {
     unpack_raw<MODE>(b, raw);
-    if constexpr (prefetch_rows<MODE>() == 2) {
-        raw = raw2;
-        w.off = min(w.off + im.stride, w.last_off);
-        load_raw(raw2, im.rsrc, w.off);  // two rows ahead (clamped to the last)
-    } else {
-        (void)raw2;
-        w.off = min(w.off + im.stride, w.last_off);
-        load_raw(raw, im.rsrc, w.off);  // prefetch the row after (clamped to the last)
-    }
+    w.off = min(w.off + im.stride, w.last_off);
+    load_raw(raw, im.rsrc, w.off);  // prefetch the row after (clamped to the last)
 #pragma unroll
     for (int a = 0; a < 6; ++a)
         Vb[a] = m.X[a] + b.X[a];
@@ -254,7 +239,7 @@ __device__ __forceinline__ void run_task(const ImgView &im, uint32_t *lds_bins, 
     w.cl = c.cl + row_cells;
     w.ch = c.ch + row_cells;
     w.uniform_cell = c.uniform_cell;
-    RawRow raw, raw2;
+    RawRow raw;
     Row A, B, C;
     uint32_t VAB[6], VBC[6], VCA[6];
     load_raw(raw, im.rsrc, w.off);
@@ -264,10 +249,6 @@ __device__ __forceinline__ void run_task(const ImgView &im, uint32_t *lds_bins, 
     unpack_raw<MODE>(B, raw);
     w.off += im.stride;
     load_raw(raw, im.rsrc, w.off);
-    if constexpr (prefetch_rows<MODE>() == 2) {
-        w.off = min(w.off + im.stride, w.last_off);
-        load_raw(raw2, im.rsrc, w.off);
-    }
 #pragma unroll
     for (int a = 0; a < 6; ++a)
         VAB[a] = A.X[a] + B.X[a];
@@ -276,7 +257,7 @@ __device__ __forceinline__ void run_task(const ImgView &im, uint32_t *lds_bins, 
     int32_t n = r1 - r0;
 #ifdef LDP_ROLLED_ROWS
     for (; n > 0; --n) {
-        step<K, MODE, HIST, CODES>(im, lds_bins, w, raw, raw2, A, B, C, VAB, VBC);
+        step<K, MODE, HIST, CODES>(im, lds_bins, w, raw, A, B, C, VAB, VBC);
         A = B;
         B = C;
 #pragma unroll
@@ -286,14 +267,14 @@ __device__ __forceinline__ void run_task(const ImgView &im, uint32_t *lds_bins, 
     (void)VCA;
 #else
     for (; n >= 3; n -= 3) {
-        step<K, MODE, HIST, CODES>(im, lds_bins, w, raw, raw2, A, B, C, VAB, VBC);
-        step<K, MODE, HIST, CODES>(im, lds_bins, w, raw, raw2, B, C, A, VBC, VCA);
-        step<K, MODE, HIST, CODES>(im, lds_bins, w, raw, raw2, C, A, B, VCA, VAB);
+        step<K, MODE, HIST, CODES>(im, lds_bins, w, raw, A, B, C, VAB, VBC);
+        step<K, MODE, HIST, CODES>(im, lds_bins, w, raw, B, C, A, VBC, VCA);
+        step<K, MODE, HIST, CODES>(im, lds_bins, w, raw, C, A, B, VCA, VAB);
     }
     if (n >= 1)
-        step<K, MODE, HIST, CODES>(im, lds_bins, w, raw, raw2, A, B, C, VAB, VBC);
+        step<K, MODE, HIST, CODES>(im, lds_bins, w, raw, A, B, C, VAB, VBC);
     if (n >= 2)
-        step<K, MODE, HIST, CODES>(im, lds_bins, w, raw, raw2, B, C, A, VBC, VCA);
+        step<K, MODE, HIST, CODES>(im, lds_bins, w, raw, B, C, A, VBC, VCA);
 #endif
 }
 
