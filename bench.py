@@ -422,6 +422,15 @@ def main():
     saved = {"signed": {j: (codes[int(code_off[j]):int(code_off[j + 1])].cpu().numpy(),
                             hist_h[j].cpu().numpy().view(np.uint32).copy()) for j in sample}}
 
+    # ---- serving, on a device that so far holds only the headline batch
+    serve = None
+    if args.serve_rates and args.serve_rates.strip():
+        rates = [int(x) for x in args.serve_rates.split(",") if x]
+        serve = {"workload": "Poisson arrivals, single uint8 images, sides log-uniform in "
+                             "[64,2048], k=3, 7x6 cells, histogram outputs; latency from "
+                             "scheduled arrival to results on the host",
+                 "runs": serve_bench(binding, synth, rates, args.serve_seconds)}
+
     # ---- variants on the same batch (they overwrite the outputs)
     variants = None
     if args.variant_steps > 0:
@@ -456,13 +465,6 @@ def main():
                           ("direct_masks", "direct_masks"), ("lbp", "lbp")):
             variants[name]["checked_images_bit_exact"] = checks.get(key)
 
-    serve = None
-    if args.serve_rates and args.serve_rates.strip():
-        rates = [int(x) for x in args.serve_rates.split(",") if x]
-        serve = {"workload": "Poisson arrivals, single uint8 images, sides log-uniform in "
-                             "[64,2048], k=3, 7x6 cells, histogram outputs; latency from "
-                             "scheduled arrival to results on the host",
-                 "runs": serve_bench(binding, synth, rates, args.serve_seconds)}
 
     desc = {"batch": "4096 x 490x640 uint8, blurred noise + 8 rectangles",
             "uneven": "10000 uint8 images, H and W uniform in [48,1024], blurred noise + rectangles",
