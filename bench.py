@@ -29,16 +29,16 @@ VALU_PEAK_T = 256 * 4 * 16 * 2.4e9 / 1e12
 # batch_kernel<k> as compiled for gfx950 (the x3-unrolled loop / 3; both
 # histogram paths counted).  tests/test_isa_counts.py recompiles the kernel and
 # checks these figures against the generated code.
-VALU_PER_ROW_STEP = {1: 470 / 3, 2: 626 / 3, 3: 662 / 3, 4: 722 / 3, 5: 722 / 3, 6: 662 / 3,
-                     7: 626 / 3, 8: 25 / 3}
+VALU_PER_ROW_STEP = {1: 431 / 3, 2: 587 / 3, 3: 623 / 3, 4: 683 / 3, 5: 683 / 3, 6: 623 / 3,
+                     7: 587 / 3, 8: 48 / 3}
 # the same for ranking by response magnitude (flags LDP_RANK_MAGNITUDE), for
 # responses computed mask by mask (LDP_DIRECT_MASKS) and for LBP labels
 # (LDP_CODE_LBP, one kernel for every k)
-VALU_PER_ROW_STEP_MAGNITUDE = {1: 824 / 3, 2: 980 / 3, 3: 1016 / 3, 4: 1076 / 3, 5: 1076 / 3,
-                               6: 1016 / 3, 7: 980 / 3, 8: 25 / 3}
-VALU_PER_ROW_STEP_DIRECT = {1: 1076 / 3, 2: 1232 / 3, 3: 1268 / 3, 4: 1328 / 3, 5: 1328 / 3,
-                            6: 1268 / 3, 7: 1232 / 3, 8: 25 / 3}
-VALU_PER_ROW_STEP_LBP = 320 / 3
+VALU_PER_ROW_STEP_MAGNITUDE = {1: 785 / 3, 2: 941 / 3, 3: 977 / 3, 4: 1037 / 3, 5: 1037 / 3,
+                               6: 977 / 3, 7: 941 / 3, 8: 48 / 3}
+VALU_PER_ROW_STEP_DIRECT = {1: 1061 / 3, 2: 1217 / 3, 3: 1253 / 3, 4: 1313 / 3, 5: 1313 / 3,
+                            6: 1253 / 3, 7: 1217 / 3, 8: 48 / 3}
+VALU_PER_ROW_STEP_LBP = 305 / 3
 # untimed work before the warm-up steps, so that timing starts at steady clocks
 DEVICE_WARMUP_S = 0.3
 

@@ -17,13 +17,13 @@
 //     S_i alone: bit i is set when S_i >= (k-th largest S).
 //   * The S_i of neighbouring pixels share partial sums: S0 and S4 are column
 //     3-sums (the right and left columns), S2 and S6 are row 3-sums (the rows
-//     above and below), and the four corner triples are a vertical pair sum
-//     plus one pixel.  Each column 3-sum serves two pixels, each row 3-sum two
-//     rows, each vertical pair four corner triples.
+//     above and below), and the four corner triples are three pixels each.
+//     Each column 3-sum serves two pixels, each row 3-sum two code rows.
+//     Every sum is one three-input add (v_add3_u32): one issue slot where
+//     chains of two-input adds over shared pair sums take more.
 //   * S_i <= 765 fits 16 bits, so two pixels share one 32-bit register.  No
-//     sum can carry out of its 16-bit field, so sums are plain 32-bit adds
-//     (on gfx950 v_add_u32 issues at twice the rate of v_pk_add_u16); only
-//     min/max use packed 16-bit instructions (v_pk_max_u16, v_pk_min_u16).
+//     sum can carry out of its 16-bit field, so sums are plain 32-bit adds;
+//     only min/max use packed 16-bit instructions.
 //     The 8 pixels of a lane are held as four pairs (c, c+4), c = 0..3,
 //     which makes the left and right neighbours of each pair another pair.
 //   * The k-th largest of eight values is a branch-free min/max network
@@ -31,7 +31,8 @@
 //   * The code bits are the sign bits of S_i + 0x8000 - t (bit 15 of a field
 //     is set exactly when S_i >= t, and no field can carry): v_perm_b32
 //     gathers four of them into four byte masks at once and v_bitop3_b32
-//     merges the eight directions.
+//     merges the eight directions.  The codes stay in the two words the
+//     gather makes (pixels 0, 1, 4, 5 and 2, 3, 6, 7).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -139,6 +140,16 @@ __device__ __forceinline__ u16x2 kth_largest(const u16x2 (&s)[8])
         return kth_network<9 - K, true>(s);
 }
 
+// Sum of three words holding two 16-bit fields each (no field carries): one
+// v_add3_u32, written as an instruction so that the compiler does not turn
+// the sums back into chains of two-input adds over shared partial sums.
+__device__ __forceinline__ uint32_t add3(uint32_t a, uint32_t b, uint32_t c)
+{
+    uint32_t r;
+    asm("v_add3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
 // ------------------------------------------------------------ image rows
 // One image row as seen by a lane: bytes B[0..9] = image columns j0..j0+9,
 // held as six pairs X[a] = (B[a], B[a+4]).  Pixel pair c (c = 0..3) is
@@ -172,12 +183,9 @@ __device__ __forceinline__ void make_row(Row &r, uint32_t u0, uint32_t u1, uint3
             r.X[a] <<= 3;  // fields <= 255 * 8: nothing crosses into the next field
     }
     // two 16-bit fields per add; no field exceeds 765, so nothing carries
-    uint32_t h1 = r.X[1] + r.X[2];
-    uint32_t h3 = r.X[3] + r.X[4];
-    r.R[0] = r.X[0] + h1;
-    r.R[1] = h1 + r.X[3];
-    r.R[2] = r.X[2] + h3;
-    r.R[3] = h3 + r.X[5];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+        r.R[c] = add3(r.X[c], r.X[c + 1], r.X[c + 2]);
 }
 
 // Raw words of one row: 16 bytes starting at the 4-aligned offset at or
@@ -221,7 +229,6 @@ __device__ __forceinline__ uint32_t mad_wm3(uint32_t x, uint32_t acc)
 // of value + (0x8000 - threshold) is set exactly when value >= threshold.
 template <int K, int MODE>
 __device__ __forceinline__ void pair_values(const Row &t, const Row &m, const Row &b,
-                                            const uint32_t (&Vt)[6], const uint32_t (&Vb)[6],
                                             const uint32_t (&col)[6], int c, uint32_t (&S)[8],
                                             uint32_t &bias)
 {
@@ -256,20 +263,20 @@ __device__ __forceinline__ void pair_values(const Row &t, const Row &m, const Ro
                 S[i] = acc;
             }
         } else {
-            S[0] = col[a + 1];           // E   column to the right
-            S[1] = Vt[a + 1] + t.X[a];   // NE  E + NE + N
-            S[2] = t.R[c];               // N   row above
-            S[3] = Vt[a - 1] + t.X[a];   // NW  N + NW + W
-            S[4] = col[a - 1];           // W   column to the left
-            S[5] = Vb[a - 1] + b.X[a];   // SW  W + SW + S
-            S[6] = b.R[c];               // S   row below
-            S[7] = Vb[a + 1] + b.X[a];   // SE  S + SE + E
+            S[0] = col[a + 1];                          // E   column to the right
+            S[1] = add3(m.X[a + 1], t.X[a + 1], t.X[a]);  // NE  E + NE + N
+            S[2] = t.R[c];                              // N   row above
+            S[3] = add3(t.X[a], t.X[a - 1], m.X[a - 1]);  // NW  N + NW + W
+            S[4] = col[a - 1];                          // W   column to the left
+            S[5] = add3(m.X[a - 1], b.X[a - 1], b.X[a]);  // SW  W + SW + S
+            S[6] = b.R[c];                              // S   row below
+            S[7] = add3(b.X[a], b.X[a + 1], m.X[a + 1]);  // SE  S + SE + E
             if constexpr (MODE == RANK_MAGNITUDE) {
                 // the sums are 8 * S_i and 8 * T (scaled rows); 3 * T is
                 // ((8 * T) >> 3) * 3 (the low 3 bits of each field are 0, so
                 // the shift moves nothing across fields), and
                 // |m_i| = |8 * S_i - 3 * T| = max - min per field
-                const uint32_t T8 = col[a + 1] + col[a - 1] + t.X[a] + b.X[a];
+                const uint32_t T8 = add3(col[a + 1], col[a - 1], t.X[a] + b.X[a]);
                 const uint32_t T1 = T8 >> 3;
                 const u16x2 T3 = V((T1 << 1) + T1);
 #pragma unroll
@@ -286,23 +293,21 @@ __device__ __forceinline__ void pair_values(const Row &t, const Row &m, const Ro
 }
 
 // Codes of the lane's 8 pixels for the code row whose image rows are t
-// (above), m (centre) and b (below).  Vt[a] = X_t[a] + X_m[a] and
-// Vb[a] = X_m[a] + X_b[a] are the vertical pair sums.  Returns the codes of
-// pixels 0..3 in `lo` and 4..7 in `hi` (byte p = pixel p).
+// (above), m (centre) and b (below): byte p of q0 is the code of pixel
+// (0, 1, 4, 5)[p], byte p of q1 that of pixel (2, 3, 6, 7)[p].
 template <int K, int MODE>
-__device__ __forceinline__ void code_row(const Row &t, const Row &m, const Row &b,
-                                         const uint32_t (&Vt)[6], const uint32_t (&Vb)[6],
-                                         uint32_t &lo, uint32_t &hi)
+__device__ __forceinline__ void code_row(const Row &t, const Row &m, const Row &b, uint32_t &q0,
+                                         uint32_t &q1)
 {
     if constexpr (K == 8 && MODE != CODE_LBP) {
         // the 8th largest is the minimum: every response reaches it
-        lo = hi = 0xFFFFFFFFu;
+        q0 = q1 = 0xFFFFFFFFu;
         return;
     } else {
         uint32_t col[6];
 #pragma unroll
         for (int a = 0; a < 6; ++a)
-            col[a] = Vt[a] + b.X[a];
+            col[a] = add3(t.X[a], m.X[a], b.X[a]);
 
         // Two halves: pixel pairs (0, 1) give the codes of pixels 0, 1, 4, 5;
         // pairs (2, 3) those of pixels 2, 3, 6, 7.  Each direction's sign
@@ -314,7 +319,7 @@ __device__ __forceinline__ void code_row(const Row &t, const Row &m, const Row &
             uint32_t S[2][8], bias[2];
 #pragma unroll
             for (int e = 0; e < 2; ++e)
-                pair_values<K, MODE>(t, m, b, Vt, Vb, col, 2 * h + e, S[e], bias[e]);
+                pair_values<K, MODE>(t, m, b, col, 2 * h + e, S[e], bias[e]);
             // bit 15 of a field of S_i + bias is set iff S_i >= threshold;
             // v_perm_b32 turns the four sign bits of a direction into byte
             // masks [first pair lo, second pair lo, first hi, second hi], and
@@ -328,10 +333,15 @@ __device__ __forceinline__ void code_row(const Row &t, const Row &m, const Row &
             }
             code[h] = acc;
         }
-        // code[0] = [px0, px1, px4, px5], code[1] = [px2, px3, px6, px7]
-        lo = __builtin_amdgcn_perm(code[1], code[0], 0x05040100u);
-        hi = __builtin_amdgcn_perm(code[1], code[0], 0x07060302u);
+        q0 = code[0];
+        q1 = code[1];
     }
+}
+
+// Code of pixel p (0..7) from the two code words of code_row.
+__device__ __forceinline__ uint32_t code_of(uint32_t q0, uint32_t q1, int p)
+{
+    return (((p & 2) ? q1 : q0) >> (8 * ((p & 1) | ((p >> 1) & 2)))) & 0xFFu;
 }
 
 }  // namespace ldp

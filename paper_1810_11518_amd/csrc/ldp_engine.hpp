@@ -139,11 +139,12 @@ __device__ __forceinline__ void unpack_raw(Row &r, const RawRow &rr)
 
 // Column group of a lane: its first code column (groups of 8, the last one
 // ends at Wc - 1) and the histogram cell column of each pixel, one byte per
-// pixel (bytes 0..3 of cl for pixels 0..3, of ch for 4..7); the discard cell
-// (nx) for the leading columns the previous group counts.
+// pixel, laid out like the code words of code_row (bytes of d0: pixels 0, 1,
+// 4, 5; of d1: pixels 2, 3, 6, 7); the discard cell (nx) for the leading
+// columns the previous group counts.
 struct Cols {
     int32_t j0;
-    uint32_t cl, ch;
+    uint32_t d0, d1;
     bool uniform_cell;  // all 8 pixels counted in one cell
 };
 
@@ -152,20 +153,21 @@ __device__ __forceinline__ Cols group_cols(const ImgView &im, const Geom &geo, i
 {
     Cols c;
     c.j0 = min(8 * g, im.Wc - 8);
-    c.cl = c.ch = 0;
+    c.d0 = c.d1 = 0;
     c.uniform_cell = false;
     if constexpr (HIST) {
         const int32_t skip = 8 * g - c.j0;
 #pragma unroll
         for (int p = 0; p < 8; ++p) {
             const uint32_t cx = ((uint32_t)(c.j0 + p) * geo.ax) / geo.bx;
-            const uint32_t d = (p < skip ? (uint32_t)geo.nx : cx) << (8 * (p & 3));
-            if (p < 4)
-                c.cl |= d;
+            const uint32_t d = (p < skip ? (uint32_t)geo.nx : cx)
+                               << (8 * ((p & 1) | ((p >> 1) & 2)));
+            if (p & 2)
+                c.d1 |= d;
             else
-                c.ch |= d;
+                c.d0 |= d;
         }
-        c.uniform_cell = c.cl == c.ch && c.cl == __builtin_amdgcn_alignbyte(c.cl, c.cl, 1);
+        c.uniform_cell = c.d0 == c.d1 && c.d0 == __builtin_amdgcn_alignbyte(c.d0, c.d0, 1);
     }
     return c;
 }
@@ -174,51 +176,80 @@ __device__ __forceinline__ Cols group_cols(const ImgView &im, const Geom &geo, i
 struct Walk {
     uint32_t off, last_off;  // image byte offset of the prefetched / last row
     uint32_t coff;           // code byte offset of the current code row
-    uint32_t cl, ch;         // per-pixel LDS cell index: cell row * (nx + 1) + cell column
+    uint32_t d0, d1;         // per-pixel LDS cell index: cell row * (nx + 1) + cell column
     bool uniform_cell;
 };
 
-// LDS byte address of the bin of pixel q (0..3) of the code word x whose LDS
-// cell indices are the bytes of d: ((cell << 8) | code) * 4.  An item's LDS
-// holds at most 64 cells, so every cell index fits its byte.
-__device__ __forceinline__ uint32_t bin_addr(uint32_t x, uint32_t d, int q)
+// LDS bins: the bin of code v in LDS cell c is the word at byte
+// base + ((c << 8) | v) * 4.  An item's LDS holds at most 64 cells (64 KB),
+// so c < 64 and the byte offset fits 16 bits.  One v_perm_b32 gathers two
+// pixels' (code, cell) byte pairs from a code word x and its cell word d into
+// the 16-bit halves of `pr`: [code a, cell a, code b, cell b] (sel picks
+// bytes qa and qb); one v_mad_u32_u16 per pixel (half * 4 + base) makes its
+// address.
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+
+__device__ __forceinline__ uint32_t lds_base(uint32_t *p)
 {
-    // byte 0 = code byte q of x, byte 1 = cell byte q of d, bytes 2, 3 = 0
-    const uint32_t sel = (uint32_t)q | ((uint32_t)(4 + q) << 8) | 0x0C0C0000u;
-    return __builtin_amdgcn_perm(d, x, sel) << 2;
+    return (uint32_t)(uintptr_t)(lds_u32 *)p;
+}
+__device__ __forceinline__ uint32_t bin_pair(uint32_t x, uint32_t d, int qa, int qb)
+{
+    const uint32_t sel = (uint32_t)qa | ((uint32_t)(4 + qa) << 8) | ((uint32_t)qb << 16) |
+                         ((uint32_t)(4 + qb) << 24);
+    return __builtin_amdgcn_perm(d, x, sel);
+}
+// Written as instructions: the compiler would otherwise mask, shift and add
+// the base in separate steps.
+__device__ __forceinline__ uint32_t bin_lo(uint32_t pr, uint32_t base)
+{
+    uint32_t r;
+    asm("v_mad_u32_u16 %0, %1, 4, %2" : "=v"(r) : "v"(pr), "s"(base));
+    return r;
+}
+__device__ __forceinline__ uint32_t bin_hi(uint32_t pr, uint32_t base)
+{
+    uint32_t r;
+    asm("v_mad_u32_u16 %0, %1, 4, %2 op_sel:[1,0,0,0]" : "=v"(r) : "v"(pr), "s"(base));
+    return r;
+}
+__device__ __forceinline__ void lds_count(uint32_t addr, uint32_t n)
+{
+    __hip_atomic_fetch_add((lds_u32 *)(uintptr_t)addr, n, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 // One code row: the next image row arrives in `raw` and becomes `b`; t and m
-// are the two rows above; Vt = X_t + X_m.  Writes Vb = X_m + X_b.
+// are the two rows above.
 template <int K, int MODE, bool HIST, bool CODES>
 __device__ __forceinline__ void step(const ImgView &im, uint32_t *lds_bins, Walk &w, RawRow &raw,
-                                     const Row &t, const Row &m, Row &b, const uint32_t (&Vt)[6],
-                                     uint32_t (&Vb)[6])
+                                     const Row &t, const Row &m, Row &b)
 {
     unpack_raw<MODE>(b, raw);
     w.off = min(w.off + im.stride, w.last_off);
     load_raw(raw, im.rsrc, w.off);  // prefetch the row after (clamped to the last)
-#pragma unroll
-    for (int a = 0; a < 6; ++a)
-        Vb[a] = m.X[a] + b.X[a];
-    uint32_t lo, hi;
-    code_row<K, MODE>(t, m, b, Vt, Vb, lo, hi);
+    uint32_t q0, q1;
+    code_row<K, MODE>(t, m, b, q0, q1);
     if constexpr (CODES) {
-        // dword stores at any byte offset (the target allows unaligned access)
-        __builtin_amdgcn_raw_buffer_store_b32(lo, im.crsrc, (int)w.coff, 0, 0);
-        __builtin_amdgcn_raw_buffer_store_b32(hi, im.crsrc, (int)(w.coff + 4), 0, 0);
+        // pixels 0-3 and 4-7 in column order; dword stores at any byte offset
+        // (the target allows unaligned access)
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_amdgcn_perm(q1, q0, 0x05040100u), im.crsrc,
+                                              (int)w.coff, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_amdgcn_perm(q1, q0, 0x07060302u), im.crsrc,
+                                              (int)(w.coff + 4), 0, 0);
         w.coff += (uint32_t)im.Wc;
     }
     if constexpr (HIST) {
-        char *lds = reinterpret_cast<char *>(lds_bins);
-        if (w.uniform_cell && lo == hi && lo == __builtin_amdgcn_alignbyte(lo, lo, 1)) {
+        const uint32_t base = lds_base(lds_bins);
+        if (w.uniform_cell && q0 == q1 && q0 == __builtin_amdgcn_alignbyte(q0, q0, 1)) {
             // eight equal codes in one cell (flat regions): one update
-            atomicAdd(reinterpret_cast<uint32_t *>(lds + bin_addr(lo, w.cl, 0)), 8u);
+            lds_count(bin_lo(bin_pair(q0, w.d0, 0, 1), base), 8u);
         } else {
 #pragma unroll
-            for (int p = 0; p < 8; ++p) {
-                const uint32_t addr = p < 4 ? bin_addr(lo, w.cl, p) : bin_addr(hi, w.ch, p - 4);
-                atomicAdd(reinterpret_cast<uint32_t *>(lds + addr), 1u);
+            for (int h = 0; h < 4; ++h) {
+                const uint32_t pr = bin_pair(h & 1 ? q1 : q0, h & 1 ? w.d1 : w.d0, h & 2, (h & 2) + 1);
+                lds_count(bin_lo(pr, base), 1u);
+                lds_count(bin_hi(pr, base), 1u);
             }
         }
     }
@@ -236,12 +267,11 @@ __device__ __forceinline__ void run_task(const ImgView &im, uint32_t *lds_bins, 
     w.coff = (uint32_t)r0 * (uint32_t)im.Wc + (uint32_t)c.j0;
     // the cell row's first LDS cell, added to every pixel's byte
     const uint32_t row_cells = (rowb >> 10) * 0x01010101u;
-    w.cl = c.cl + row_cells;
-    w.ch = c.ch + row_cells;
+    w.d0 = c.d0 + row_cells;
+    w.d1 = c.d1 + row_cells;
     w.uniform_cell = c.uniform_cell;
     RawRow raw;
     Row A, B, C;
-    uint32_t VAB[6], VBC[6], VCA[6];
     load_raw(raw, im.rsrc, w.off);
     unpack_raw<MODE>(A, raw);
     w.off += im.stride;
@@ -249,33 +279,18 @@ __device__ __forceinline__ void run_task(const ImgView &im, uint32_t *lds_bins, 
     unpack_raw<MODE>(B, raw);
     w.off += im.stride;
     load_raw(raw, im.rsrc, w.off);
-#pragma unroll
-    for (int a = 0; a < 6; ++a)
-        VAB[a] = A.X[a] + B.X[a];
-    // the three rows rotate through A, B, C (and the vertical pair sums
-    // through VAB, VBC, VCA) so no registers are copied between rows
+    // the three rows rotate through A, B, C so no registers are copied
+    // between rows
     int32_t n = r1 - r0;
-#ifdef LDP_ROLLED_ROWS
-    for (; n > 0; --n) {
-        step<K, MODE, HIST, CODES>(im, lds_bins, w, raw, A, B, C, VAB, VBC);
-        A = B;
-        B = C;
-#pragma unroll
-        for (int a = 0; a < 6; ++a)
-            VAB[a] = VBC[a];
-    }
-    (void)VCA;
-#else
     for (; n >= 3; n -= 3) {
-        step<K, MODE, HIST, CODES>(im, lds_bins, w, raw, A, B, C, VAB, VBC);
-        step<K, MODE, HIST, CODES>(im, lds_bins, w, raw, B, C, A, VBC, VCA);
-        step<K, MODE, HIST, CODES>(im, lds_bins, w, raw, C, A, B, VCA, VAB);
+        step<K, MODE, HIST, CODES>(im, lds_bins, w, raw, A, B, C);
+        step<K, MODE, HIST, CODES>(im, lds_bins, w, raw, B, C, A);
+        step<K, MODE, HIST, CODES>(im, lds_bins, w, raw, C, A, B);
     }
     if (n >= 1)
-        step<K, MODE, HIST, CODES>(im, lds_bins, w, raw, A, B, C, VAB, VBC);
+        step<K, MODE, HIST, CODES>(im, lds_bins, w, raw, A, B, C);
     if (n >= 2)
-        step<K, MODE, HIST, CODES>(im, lds_bins, w, raw, B, C, A, VBC, VCA);
-#endif
+        step<K, MODE, HIST, CODES>(im, lds_bins, w, raw, B, C, A);
 }
 
 // Code rows [r0, r1) of a code map narrower than 8 columns: one lane, the
@@ -292,10 +307,6 @@ __device__ void run_task_narrow(const ImgView &im, uint32_t *lds_bins, uint32_t 
     unpack_raw<MODE>(t, raw);
     load_raw(raw, im.rsrc, off + im.stride);
     unpack_raw<MODE>(m, raw);
-    uint32_t Vt[6], Vb[6];
-#pragma unroll
-    for (int a = 0; a < 6; ++a)
-        Vt[a] = t.X[a] + m.X[a];
     uint32_t cb[8];
     if constexpr (HIST) {
         for (int p = 0; p < 8; ++p) {
@@ -307,29 +318,22 @@ __device__ void run_task_narrow(const ImgView &im, uint32_t *lds_bins, uint32_t 
     for (int32_t r = r0; r < r1; ++r) {
         load_raw(raw, im.rsrc, off + (uint32_t)(r + 2 - r0) * im.stride);
         unpack_raw<MODE>(b, raw);
-#pragma unroll
-        for (int a = 0; a < 6; ++a)
-            Vb[a] = m.X[a] + b.X[a];
-        uint32_t lo, hi;
-        code_row<K, MODE>(t, m, b, Vt, Vb, lo, hi);
+        uint32_t q0, q1;
+        code_row<K, MODE>(t, m, b, q0, q1);
         if constexpr (CODES) {
             const uint32_t coff = (uint32_t)r * (uint32_t)im.Wc;
             for (int p = 0; p < nvalid; ++p)
-                __builtin_amdgcn_raw_buffer_store_b8((uint8_t)((p < 4 ? lo : hi) >> (8 * (p & 3))),
-                                                     im.crsrc, (int)(coff + p), 0, 0);
+                __builtin_amdgcn_raw_buffer_store_b8((uint8_t)code_of(q0, q1, p), im.crsrc,
+                                                     (int)(coff + p), 0, 0);
         }
         if constexpr (HIST) {
             char *lds = reinterpret_cast<char *>(lds_bins);
-            for (int p = 0; p < 8; ++p) {
-                const uint32_t code = ((p < 4 ? lo : hi) >> (8 * (p & 3))) & 0xFFu;
-                atomicAdd(reinterpret_cast<uint32_t *>(lds + (cb[p] | (code << 2))), 1u);
-            }
+            for (int p = 0; p < 8; ++p)
+                atomicAdd(reinterpret_cast<uint32_t *>(lds + (cb[p] | (code_of(q0, q1, p) << 2))),
+                          1u);
         }
         t = m;
         m = b;
-#pragma unroll
-        for (int a = 0; a < 6; ++a)
-            Vt[a] = Vb[a];
     }
 }
 
