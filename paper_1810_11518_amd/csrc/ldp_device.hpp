@@ -310,9 +310,7 @@ __device__ __forceinline__ void code_row(const Row &t, const Row &m, const Row &
             col[a] = add3(t.X[a], m.X[a], b.X[a]);
 
         // Two halves: pixel pairs (0, 1) give the codes of pixels 0, 1, 4, 5;
-        // pairs (2, 3) those of pixels 2, 3, 6, 7.  Each direction's sign
-        // bits are folded into the code as soon as they exist, which keeps
-        // few values live.
+        // pairs (2, 3) those of pixels 2, 3, 6, 7.
         uint32_t code[2];
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
@@ -320,15 +318,25 @@ __device__ __forceinline__ void code_row(const Row &t, const Row &m, const Row &
 #pragma unroll
             for (int e = 0; e < 2; ++e)
                 pair_values<K, MODE>(t, m, b, col, 2 * h + e, S[e], bias[e]);
-            // bit 15 of a field of S_i + bias is set iff S_i >= threshold;
+            // bit 15 of a field of S_i + bias is set iff S_i >= threshold.
+            // The 16 adds are kept together (scheduling barriers around
+            // them): on gfx950 a run of independent 32-bit adds issues faster
+            // than adds spread between other instructions.
+            uint32_t x[2][8];
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int e = 0; e < 2; ++e)
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+                    x[e][i] = S[e][i] + bias[e];
+            __builtin_amdgcn_sched_barrier(0);
             // v_perm_b32 turns the four sign bits of a direction into byte
             // masks [first pair lo, second pair lo, first hi, second hi], and
             // bit i of every byte is taken from direction i.
-            uint32_t acc = __builtin_amdgcn_perm(S[1][0] + bias[1], S[0][0] + bias[0], 0x0B090A08u);
+            uint32_t acc = __builtin_amdgcn_perm(x[1][0], x[0][0], 0x0B090A08u);
 #pragma unroll
             for (int i = 1; i < 8; ++i) {
-                const uint32_t msk = __builtin_amdgcn_perm(S[1][i] + bias[1], S[0][i] + bias[0],
-                                                           0x0B090A08u);
+                const uint32_t msk = __builtin_amdgcn_perm(x[1][i], x[0][i], 0x0B090A08u);
                 acc = __builtin_amdgcn_bitop3_b32(0x01010101u << i, msk, acc, 0xCA);
             }
             code[h] = acc;

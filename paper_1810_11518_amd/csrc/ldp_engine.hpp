@@ -157,9 +157,17 @@ __device__ __forceinline__ Cols group_cols(const ImgView &im, const Geom &geo, i
     c.uniform_cell = false;
     if constexpr (HIST) {
         const int32_t skip = 8 * g - c.j0;
+        // Cells at least 8 columns wide (the usual case, decided per image):
+        // the 8 columns meet at most one cell boundary, so two divisions (the
+        // first column's cell and the next cell's first column) place them
+        // all.  Narrower cells: one division per column.
+        const bool wide = geo.bx >= 8u * geo.ax;
+        const uint32_t cx0 = ((uint32_t)c.j0 * geo.ax) / geo.bx;
+        const uint32_t next = wide ? (uint32_t)geom_col_start(geo, (int32_t)cx0 + 1, im.Wc) : 0u;
 #pragma unroll
         for (int p = 0; p < 8; ++p) {
-            const uint32_t cx = ((uint32_t)(c.j0 + p) * geo.ax) / geo.bx;
+            const uint32_t j = (uint32_t)(c.j0 + p);
+            const uint32_t cx = wide ? cx0 + (j >= next ? 1u : 0u) : (j * geo.ax) / geo.bx;
             const uint32_t d = (p < skip ? (uint32_t)geo.nx : cx)
                                << (8 * ((p & 1) | ((p >> 1) & 2)));
             if (p & 2)
