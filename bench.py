@@ -27,18 +27,19 @@ VALU_PEAK_T = 256 * 4 * 16 * 2.4e9 / 1e12
 # Algorithmic VALU work of the batched kernel: wave instructions per 8-pixel
 # row step of a lane (one wave covers 512 code pixels) in the main row loop of
 # batch_kernel<k> as compiled for gfx950 (the x3-unrolled loop / 3; both
-# histogram paths counted).  tests/test_isa_counts.py recompiles the kernel and
-# checks these figures against the generated code.
-VALU_PER_ROW_STEP = {1: 431 / 3, 2: 587 / 3, 3: 623 / 3, 4: 683 / 3, 5: 683 / 3, 6: 623 / 3,
-                     7: 587 / 3, 8: 48 / 3}
+# histogram paths counted; the loop with the fewest instructions, which waves
+# whose rows start 4-aligned run).  tests/test_isa_counts.py recompiles the
+# kernel and checks these figures against the generated code.
+VALU_PER_ROW_STEP = {1: 413 / 3, 2: 569 / 3, 3: 605 / 3, 4: 665 / 3, 5: 665 / 3, 6: 605 / 3,
+                     7: 569 / 3, 8: 45 / 3}
 # the same for ranking by response magnitude (flags LDP_RANK_MAGNITUDE), for
 # responses computed mask by mask (LDP_DIRECT_MASKS) and for LBP labels
 # (LDP_CODE_LBP, one kernel for every k)
-VALU_PER_ROW_STEP_MAGNITUDE = {1: 785 / 3, 2: 941 / 3, 3: 977 / 3, 4: 1037 / 3, 5: 1037 / 3,
-                               6: 977 / 3, 7: 941 / 3, 8: 48 / 3}
-VALU_PER_ROW_STEP_DIRECT = {1: 1061 / 3, 2: 1217 / 3, 3: 1253 / 3, 4: 1313 / 3, 5: 1313 / 3,
-                            6: 1253 / 3, 7: 1217 / 3, 8: 48 / 3}
-VALU_PER_ROW_STEP_LBP = 305 / 3
+VALU_PER_ROW_STEP_MAGNITUDE = {1: 767 / 3, 2: 923 / 3, 3: 959 / 3, 4: 1019 / 3, 5: 1019 / 3,
+                               6: 959 / 3, 7: 923 / 3, 8: 45 / 3}
+VALU_PER_ROW_STEP_DIRECT = {1: 1043 / 3, 2: 1199 / 3, 3: 1235 / 3, 4: 1295 / 3, 5: 1295 / 3,
+                            6: 1235 / 3, 7: 1199 / 3, 8: 45 / 3}
+VALU_PER_ROW_STEP_LBP = 287 / 3
 # untimed work before the warm-up steps, so that timing starts at steady clocks
 DEVICE_WARMUP_S = 0.3
 

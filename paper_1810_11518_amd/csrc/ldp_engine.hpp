@@ -117,24 +117,39 @@ __host__ __device__ __forceinline__ uint32_t hist_row_bytes(int32_t nx)
 
 // Loads one image row for the lane: 16 bytes from the 4-aligned offset at or
 // below the lane's first byte (aligned dwords never leave the image's last
-// page), then realigns them.
+// page), then realigns them.  ALIGNED: the lane's first byte is 4-aligned
+// (a wave-wide fact, decided per task), so 12 bytes cover its 10 and no
+// realignment is needed.
+template <bool ALIGNED>
 __device__ __forceinline__ void load_raw(RawRow &rr, __amdgpu_buffer_rsrc_t rsrc, uint32_t off)
 {
-    rr.s = off & 3u;
-    const uint32_t a = off & ~3u;
-    rr.w[0] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)a, 0, 0);
-    rr.w[1] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)(a + 4), 0, 0);
-    rr.w[2] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)(a + 8), 0, 0);
-    rr.w[3] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)(a + 12), 0, 0);
+    if constexpr (ALIGNED) {
+        rr.s = 0;
+        rr.w[0] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)off, 0, 0);
+        rr.w[1] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)(off + 4), 0, 0);
+        rr.w[2] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)(off + 8), 0, 0);
+        rr.w[3] = 0;
+    } else {
+        rr.s = off & 3u;
+        const uint32_t a = off & ~3u;
+        rr.w[0] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)a, 0, 0);
+        rr.w[1] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)(a + 4), 0, 0);
+        rr.w[2] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)(a + 8), 0, 0);
+        rr.w[3] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)(a + 12), 0, 0);
+    }
 }
 
-template <int MODE>
+template <int MODE, bool ALIGNED>
 __device__ __forceinline__ void unpack_raw(Row &r, const RawRow &rr)
 {
-    uint32_t u0 = __builtin_amdgcn_alignbyte(rr.w[1], rr.w[0], rr.s);
-    uint32_t u1 = __builtin_amdgcn_alignbyte(rr.w[2], rr.w[1], rr.s);
-    uint32_t u2 = __builtin_amdgcn_alignbyte(rr.w[3], rr.w[2], rr.s);
-    make_row<MODE>(r, u0, u1, u2);
+    if constexpr (ALIGNED) {
+        make_row<MODE>(r, rr.w[0], rr.w[1], rr.w[2]);
+    } else {
+        uint32_t u0 = __builtin_amdgcn_alignbyte(rr.w[1], rr.w[0], rr.s);
+        uint32_t u1 = __builtin_amdgcn_alignbyte(rr.w[2], rr.w[1], rr.s);
+        uint32_t u2 = __builtin_amdgcn_alignbyte(rr.w[3], rr.w[2], rr.s);
+        make_row<MODE>(r, u0, u1, u2);
+    }
 }
 
 // Column group of a lane: its first code column (groups of 8, the last one
@@ -229,13 +244,13 @@ __device__ __forceinline__ void lds_count(uint32_t addr, uint32_t n)
 
 // One code row: the next image row arrives in `raw` and becomes `b`; t and m
 // are the two rows above.
-template <int K, int MODE, bool HIST, bool CODES>
+template <int K, int MODE, bool HIST, bool CODES, bool ALIGNED>
 __device__ __forceinline__ void step(const ImgView &im, uint32_t *lds_bins, Walk &w, RawRow &raw,
                                      const Row &t, const Row &m, Row &b)
 {
-    unpack_raw<MODE>(b, raw);
+    unpack_raw<MODE, ALIGNED>(b, raw);
     w.off = min(w.off + im.stride, w.last_off);
-    load_raw(raw, im.rsrc, w.off);  // prefetch the row after (clamped to the last)
+    load_raw<ALIGNED>(raw, im.rsrc, w.off);  // prefetch the row after (clamped to the last)
     uint32_t q0, q1;
     code_row<K, MODE>(t, m, b, q0, q1);
     if constexpr (CODES) {
@@ -263,6 +278,32 @@ __device__ __forceinline__ void step(const ImgView &im, uint32_t *lds_bins, Walk
     }
 }
 
+// The row walk of a task from its first code row: n rows.
+template <int K, int MODE, bool HIST, bool CODES, bool ALIGNED>
+__device__ __forceinline__ void walk_rows(const ImgView &im, uint32_t *lds_bins, Walk &w, int32_t n)
+{
+    RawRow raw;
+    Row A, B, C;
+    load_raw<ALIGNED>(raw, im.rsrc, w.off);
+    unpack_raw<MODE, ALIGNED>(A, raw);
+    w.off += im.stride;
+    load_raw<ALIGNED>(raw, im.rsrc, w.off);
+    unpack_raw<MODE, ALIGNED>(B, raw);
+    w.off += im.stride;
+    load_raw<ALIGNED>(raw, im.rsrc, w.off);
+    // the three rows rotate through A, B, C so no registers are copied
+    // between rows
+    for (; n >= 3; n -= 3) {
+        step<K, MODE, HIST, CODES, ALIGNED>(im, lds_bins, w, raw, A, B, C);
+        step<K, MODE, HIST, CODES, ALIGNED>(im, lds_bins, w, raw, B, C, A);
+        step<K, MODE, HIST, CODES, ALIGNED>(im, lds_bins, w, raw, C, A, B);
+    }
+    if (n >= 1)
+        step<K, MODE, HIST, CODES, ALIGNED>(im, lds_bins, w, raw, A, B, C);
+    if (n >= 2)
+        step<K, MODE, HIST, CODES, ALIGNED>(im, lds_bins, w, raw, B, C, A);
+}
+
 // Run code rows [r0, r1) of the column group `c`; with HIST they all lie in
 // the cell row whose histograms start at LDS byte `rowb`.
 template <int K, int MODE, bool HIST, bool CODES>
@@ -278,27 +319,12 @@ __device__ __forceinline__ void run_task(const ImgView &im, uint32_t *lds_bins, 
     w.d0 = c.d0 + row_cells;
     w.d1 = c.d1 + row_cells;
     w.uniform_cell = c.uniform_cell;
-    RawRow raw;
-    Row A, B, C;
-    load_raw(raw, im.rsrc, w.off);
-    unpack_raw<MODE>(A, raw);
-    w.off += im.stride;
-    load_raw(raw, im.rsrc, w.off);
-    unpack_raw<MODE>(B, raw);
-    w.off += im.stride;
-    load_raw(raw, im.rsrc, w.off);
-    // the three rows rotate through A, B, C so no registers are copied
-    // between rows
-    int32_t n = r1 - r0;
-    for (; n >= 3; n -= 3) {
-        step<K, MODE, HIST, CODES>(im, lds_bins, w, raw, A, B, C);
-        step<K, MODE, HIST, CODES>(im, lds_bins, w, raw, B, C, A);
-        step<K, MODE, HIST, CODES>(im, lds_bins, w, raw, C, A, B);
-    }
-    if (n >= 1)
-        step<K, MODE, HIST, CODES>(im, lds_bins, w, raw, A, B, C);
-    if (n >= 2)
-        step<K, MODE, HIST, CODES>(im, lds_bins, w, raw, B, C, A);
+    // every row of every lane of the wave starts 4-aligned: the walk without
+    // realignment (typical: all column groups but an image's last one)
+    if (__all(((w.off | im.stride) & 3u) == 0))
+        walk_rows<K, MODE, HIST, CODES, true>(im, lds_bins, w, r1 - r0);
+    else
+        walk_rows<K, MODE, HIST, CODES, false>(im, lds_bins, w, r1 - r0);
 }
 
 // Code rows [r0, r1) of a code map narrower than 8 columns: one lane, the
@@ -311,10 +337,10 @@ __device__ void run_task_narrow(const ImgView &im, uint32_t *lds_bins, uint32_t 
     const uint32_t off = im.off0 + (uint32_t)r0 * im.stride;
     RawRow raw;
     Row t, m, b;
-    load_raw(raw, im.rsrc, off);
-    unpack_raw<MODE>(t, raw);
-    load_raw(raw, im.rsrc, off + im.stride);
-    unpack_raw<MODE>(m, raw);
+    load_raw<false>(raw, im.rsrc, off);
+    unpack_raw<MODE, false>(t, raw);
+    load_raw<false>(raw, im.rsrc, off + im.stride);
+    unpack_raw<MODE, false>(m, raw);
     uint32_t cb[8];
     if constexpr (HIST) {
         for (int p = 0; p < 8; ++p) {
@@ -324,8 +350,8 @@ __device__ void run_task_narrow(const ImgView &im, uint32_t *lds_bins, uint32_t 
         }
     }
     for (int32_t r = r0; r < r1; ++r) {
-        load_raw(raw, im.rsrc, off + (uint32_t)(r + 2 - r0) * im.stride);
-        unpack_raw<MODE>(b, raw);
+        load_raw<false>(raw, im.rsrc, off + (uint32_t)(r + 2 - r0) * im.stride);
+        unpack_raw<MODE, false>(b, raw);
         uint32_t q0, q1;
         code_row<K, MODE>(t, m, b, q0, q1);
         if constexpr (CODES) {
