@@ -105,13 +105,20 @@ _lib = None
 
 
 def load():
-    """Load libldp.so (raises if it has not been built)."""
+    """Load libldp.so (raises if it has not been built).
+
+    torch is imported first: a PyTorch ROCm build can carry its own HIP
+    runtime library, and libldp.so must bind to that one (the library's HIP
+    dependency resolves to the runtime already in the process).  Loaded
+    before torch, the library would bring in a second HIP runtime, whose
+    context does not know torch's device memory."""
     global _lib
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError("libldp.so is not built (%s); run __graft_entry__.build() or "
                            "python -m paper_1810_11518_amd.build" % LIB_PATH)
+    import torch  # noqa: F401  (see above)
     lib = ctypes.CDLL(LIB_PATH)
     p, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
     sig = {

@@ -54,8 +54,8 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v)
 // pixels (every image's cell grid follows from its own size).
 template <int K, int MODE>
 // The item number is broadcast through the LDS word after the histograms
-// (`item_slot`, in words): with no static LDS the histograms start at LDS
-// address 0, so a bin address needs no base added.
+// (`item_slot`, in words): the kernel has no static LDS, and the histograms
+// start at the beginning of its dynamic LDS.
 __global__ void __launch_bounds__(1024) LDP_BATCH_ATTR batch_kernel(const ldp_image_desc *__restrict__ descs,
                                                      Meta *meta, int32_t gy, int32_t gx,
                                                      int32_t windows, int32_t item_slot)
@@ -469,3 +469,13 @@ int ldp_batch_plan_destroy(ldp_batch_plan *p)
 }
 
 }  // extern "C"
+
+namespace ldp {
+int warm_plan(ldp_batch_plan *p, hipStream_t s)
+{
+    int rc = ldp_batch_plan_set(p, nullptr, 0, (ldp_stream_t)s);
+    if (rc != LDP_OK)
+        return rc;
+    return hipGraphLaunch(p->exec, s) == hipSuccess ? LDP_OK : LDP_ERR_HIP;
+}
+}  // namespace ldp

@@ -461,15 +461,17 @@ __device__ __forceinline__ void fused_item(const ImgView &im, uint32_t *lds, con
         }
     }
     __syncthreads();
+    // the histograms are device memory: global (not flat) stores and atomics
+    typedef __attribute__((address_space(1))) uint32_t global_u32;
     for (int32_t r = 0; r < cy1 - cy0; ++r) {
         const uint32_t *src = lds + r * row_words;
-        uint32_t *dst = hist + (int64_t)(cy0 + r) * geo.nx * 256;
+        global_u32 *dst = (global_u32 *)(hist + (int64_t)(cy0 + r) * geo.nx * 256);
         for (int32_t i = tid; i < geo.nx * 256; i += nthreads) {
             const uint32_t v = src[i];
             if (!atomic_flush)
                 dst[i] = v;
             else if (v)
-                atomicAdd(dst + i, v);
+                __hip_atomic_fetch_add(dst + i, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
 }

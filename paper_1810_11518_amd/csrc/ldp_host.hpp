@@ -57,4 +57,10 @@ int launch_extract(const uint8_t *img, int32_t H, int32_t W, int64_t stride, int
                    int32_t flags, int32_t gy, int32_t gx, bool windows, uint8_t *codes,
                    uint32_t *hist, hipStream_t s);
 
+// Sets an empty batch on plan `p` and launches its graph on `s` anyway (its
+// workgroups find no work items and exit): the first launch on a stream
+// pays one-time runtime set-up, which a server takes at creation instead of
+// on its first requests.
+int warm_plan(ldp_batch_plan *p, hipStream_t s);
+
 }  // namespace ldp

@@ -326,6 +326,32 @@ int ldp_server_create(ldp_server **out, const ldp_server_config *cfg)
             }
             s->plans.push_back(p);
         }
+        // Warm every launch slot: the first graph launch and the first copies
+        // on a stream pay one-time runtime set-up (milliseconds), which would
+        // otherwise land on the first requests that reach a slot once the
+        // load spreads over several slots.
+        uint8_t *h = nullptr;
+        if (hipHostMalloc(&h, 4096) != hipSuccess) {
+            release_server(s);
+            return LDP_ERR_NO_MEMORY;
+        }
+        int wrc = LDP_OK;
+        for (int i = 0; i < c.depth && wrc == LDP_OK; ++i) {
+            hipStream_t st = s->streams[i];
+            wrc = ldp::warm_plan(s->plans[i], st);
+            if (wrc == LDP_OK &&
+                (hipMemcpyAsync(s->d_pool, h, 4096, hipMemcpyHostToDevice, st) != hipSuccess ||
+                 hipMemcpy2DAsync(s->d_pool, 32, h, 64, 32, 8, hipMemcpyHostToDevice, st) !=
+                     hipSuccess ||
+                 hipMemcpyAsync(h, s->d_pool, 4096, hipMemcpyDeviceToHost, st) != hipSuccess ||
+                 hipStreamSynchronize(st) != hipSuccess))
+                wrc = LDP_ERR_HIP;
+        }
+        (void)hipHostFree(h);
+        if (wrc != LDP_OK) {
+            release_server(s);
+            return wrc;
+        }
     }
     s->th = std::thread(dispatcher, s);
     *out = s;
