@@ -326,8 +326,11 @@ typedef struct ldp_server_stats {
 double ldp_now(void);
 
 /* Create a server (allocates the pool, streams and batch plans; starts the
- * dispatcher thread).  Errors: LDP_ERR_INVALID_ARG, LDP_ERR_NO_MEMORY,
- * LDP_ERR_HIP. */
+ * dispatcher thread).  Without dry_run it also launches every slot's batch
+ * graph once on an empty batch and runs one small copy of each kind on the
+ * slot's stream, synchronously, so that one-time runtime set-up does not
+ * fall on the first requests (a few milliseconds at creation).  Errors:
+ * LDP_ERR_INVALID_ARG, LDP_ERR_NO_MEMORY, LDP_ERR_HIP. */
 int ldp_server_create(ldp_server **server, const ldp_server_config *config);
 
 /* Queue one request.  img is HOST memory, H x W with pitch `stride`; codes
