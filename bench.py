@@ -97,6 +97,27 @@ def algorithmic_bytes(Hs, Ws, cells):
     return int((H * W + (H - 2) * (W - 2)).sum() + len(H) * cells[0] * cells[1] * 1024)
 
 
+def copy_rate(torch, dev, mib=1024, reps=5):
+    """Achievable HBM rate on this device: a plain device-to-device copy of
+    `mib` MiB (torch's copy kernel), best of `reps`, HIP events; GB/s of
+    bytes read plus written."""
+    src = torch.ones((mib << 20) // 4, dtype=torch.int32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    best = None
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del src, dst
+    return 2.0 * (mib << 20) / (best * 1e-3) / 1e9
+
+
 def _timed(torch, fn, steps, warmup=3):
     """Mean ms per call of fn over `steps` calls, HIP events on the current stream."""
     for _ in range(warmup):
@@ -452,6 +473,7 @@ def main():
 
     abytes = algorithmic_bytes(Hs, Ws, cells)
     achieved = abytes / (ms_event * 1e-3) / 1e9
+    copy_gbs = copy_rate(torch, dev)
     mpix = pixels / (ms_step * 1e-3) / 1e6
     mpix_plain = pixels / (ms_plain * 1e-3) / 1e6 if ms_plain else None
 
@@ -508,7 +530,10 @@ def main():
                      "traffic": traffic,
                      "hbm": {"achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                              "frac": round(achieved / HBM_PEAK_GBS, 4),
-                             "algorithmic_bytes_per_launch": abytes},
+                             "algorithmic_bytes_per_launch": abytes,
+                             "copy_achieved": round(copy_gbs, 1),
+                             "frac_of_copy": round(achieved / copy_gbs, 4),
+                             "copy": "1 GiB device-to-device copy, best of 5, read + write bytes"},
                      "kernel": "batch_kernel<%d>" % k},
         "plain": None if not ms_plain else {
             "value": round(mpix_plain, 1), "unit": "Mpixel/s", "ms_per_step": round(ms_plain, 3),
