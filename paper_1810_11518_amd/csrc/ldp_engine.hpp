@@ -61,6 +61,17 @@ __host__ __device__ __forceinline__ int32_t cell_start(int32_t c, int32_t n, int
     return (int32_t)(((uint32_t)c * (uint32_t)n + (uint32_t)cells - 1u) / (uint32_t)cells);
 }
 
+// floor(x / d) for x < 2^20 and 1 <= d < 2^20, without the 32-bit division
+// sequence: q = trunc(x * rcp(d)) in f32.  v_rcp_f32 is within 1 ulp, so
+// x * rcp(d) is within x/d * 2^-22 < 1/(4d) of x/d; writing x/d = m + f/d
+// (0 <= f < d), q is m when f > 0 and m or m - 1 when f = 0, and the
+// remainder test adds the missing one.
+__device__ __forceinline__ uint32_t udiv_small(uint32_t x, uint32_t d)
+{
+    const uint32_t q = (uint32_t)((float)x * __builtin_amdgcn_rcpf((float)d));
+    return q + (x - __umul24(q, d) >= d ? 1u : 0u);
+}
+
 // Histogram cells of a code map: code row r lies in cell row r*ay/by, code
 // column j in cell column j*ax/bx; ny x nx cells.
 //   cells (Eqs. 4-5 over a grid): ay = cells_y, by = Hc, ax = cells_x, bx = Wc;
@@ -393,8 +404,11 @@ __device__ __forceinline__ void fused_item(const ImgView &im, uint32_t *lds, con
     const int tid = threadIdx.x, nthreads = blockDim.x;
     const uint32_t row_bytes = hist_row_bytes(geo.nx);
     const int32_t row_words = (geo.nx + 1) * 256;
-    for (int32_t i = tid; i < (cy1 - cy0) * row_words; i += nthreads)
-        lds[i] = 0;
+    // 16-byte LDS writes (the histograms start 16-byte aligned and every
+    // cell row is a multiple of 1 KB)
+    uint4 *lds4 = reinterpret_cast<uint4 *>(lds);
+    for (int32_t i = tid; i < (cy1 - cy0) * (row_words / 4); i += nthreads)
+        lds4[i] = make_uint4(0u, 0u, 0u, 0u);
     __syncthreads();
     // code rows [a, b) of the current cell row inside [r0, r1)
     int32_t a = max(r0, geom_row_start(geo, cy0, im.Hc));
@@ -416,9 +430,11 @@ __device__ __forceinline__ void fused_item(const ImgView &im, uint32_t *lds, con
         }
     } else {
         const int32_t ngroups = (im.Wc + 7) / 8;
-        const int32_t q = nthreads / ngroups;
+        // operands below 2^16 (threads <= 1024, rows <= 65534): udiv_small
+        const int32_t q = (int32_t)udiv_small((uint32_t)nthreads, (uint32_t)ngroups);
         if (q >= 1) {
-            const int32_t cap = (b - a + min_task_rows - 1) / min_task_rows;
+            const int32_t cap = (int32_t)udiv_small((uint32_t)(b - a + min_task_rows - 1),
+                                                    (uint32_t)min_task_rows);
             const int32_t nsub = max(1, min(q, cap));
             // groups with one band more (only when bands stay long enough)
             const int32_t nx = (nsub == q && cap > q) ? nthreads - q * ngroups : 0;
@@ -426,12 +442,13 @@ __device__ __forceinline__ void fused_item(const ImgView &im, uint32_t *lds, con
             if (tid < base + (nsub + 1) * nx) {
                 uint32_t g, sb, nb;
                 if (tid < base) {
-                    g = (uint32_t)tid % (uint32_t)(ngroups - nx);
-                    sb = (uint32_t)tid / (uint32_t)(ngroups - nx);
+                    const uint32_t m = (uint32_t)(ngroups - nx);
+                    sb = udiv_small((uint32_t)tid, m);
+                    g = (uint32_t)tid - sb * m;
                     nb = (uint32_t)nsub;
                 } else {
-                    g = (uint32_t)(ngroups - nx) + (uint32_t)(tid - base) % (uint32_t)nx;
-                    sb = (uint32_t)(tid - base) / (uint32_t)nx;
+                    sb = udiv_small((uint32_t)(tid - base), (uint32_t)nx);
+                    g = (uint32_t)(ngroups - nx) + (uint32_t)(tid - base) - sb * (uint32_t)nx;
                     nb = (uint32_t)nsub + 1;
                 }
                 const Cols c = group_cols<true>(im, geo, (int32_t)g);
@@ -440,10 +457,13 @@ __device__ __forceinline__ void fused_item(const ImgView &im, uint32_t *lds, con
                         a = b;
                         b = min(r1, geom_row_start(geo, cy + 1, im.Hc));
                     }
-                    // 32-bit arithmetic: nr * nb <= 2^16 * 2^10
+                    // band sb of nb over nr rows: [nr*sb/nb, nr*(sb+1)/nb).  With
+                    // nr = qn*nb + rn, nr*s/nb = qn*s + rn*s/nb, and rn*s < nb^2
+                    // <= 2^20 (nb <= 1024 threads)
                     const uint32_t nr = (uint32_t)max(b - a, 0);
-                    const int32_t a0 = a + (int32_t)((nr * sb) / nb);
-                    const int32_t a1 = a + (int32_t)((nr * (sb + 1)) / nb);
+                    const uint32_t qn = udiv_small(nr, nb), rn = nr - qn * nb;
+                    const int32_t a0 = a + (int32_t)(qn * sb + udiv_small(rn * sb, nb));
+                    const int32_t a1 = a + (int32_t)(qn * (sb + 1) + udiv_small(rn * (sb + 1), nb));
                     if (a1 > a0)
                         run_task<K, MODE, true, CODES>(im, lds, (cy - cy0) * row_bytes, c, a0, a1);
                 }
@@ -463,6 +483,18 @@ __device__ __forceinline__ void fused_item(const ImgView &im, uint32_t *lds, con
     __syncthreads();
     // the histograms are device memory: global (not flat) stores and atomics
     typedef __attribute__((address_space(1))) uint32_t global_u32;
+    if (!atomic_flush && ((uintptr_t)hist & 15u) == 0) {
+        // 16 bytes per access: every cell row is nx * 1 KB in both places
+        typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+        typedef __attribute__((address_space(1))) u32x4 global_u32x4;
+        for (int32_t r = 0; r < cy1 - cy0; ++r) {
+            const u32x4 *src = reinterpret_cast<const u32x4 *>(lds + r * row_words);
+            global_u32x4 *dst = (global_u32x4 *)(hist + (int64_t)(cy0 + r) * geo.nx * 256);
+            for (int32_t i = tid; i < geo.nx * 64; i += nthreads)
+                dst[i] = src[i];
+        }
+        return;
+    }
     for (int32_t r = 0; r < cy1 - cy0; ++r) {
         const uint32_t *src = lds + r * row_words;
         global_u32 *dst = (global_u32 *)(hist + (int64_t)(cy0 + r) * geo.nx * 256);

@@ -79,6 +79,38 @@ def test_uneven_batch_matches_oracle(lib, k):
         b.check(j, k, (7, 6))
 
 
+def test_histograms_in_buffers_not_16_byte_aligned(lib):
+    """Each image's histograms 4 bytes past a 16-byte boundary: the flush
+    goes word by word instead of 16 bytes at a time; same results (batch
+    plan, and single-image extract with and without split cell rows)."""
+    r = np.random.default_rng(61)
+    n = 12
+    cells = (7, 6)
+    Hs, Ws = r.integers(20, 400, n), r.integers(20, 500, n)
+    b = Batch(Hs, Ws, synth.KIND_BLUR_RECTS, 62, cells)
+    per = cells[0] * cells[1] * 256
+    big = torch.full((n * per + 4,), 7, dtype=torch.int32, device="cuda")
+    hists = [big[1 + j * per:1 + (j + 1) * per] for j in range(n)]
+    assert all(h.data_ptr() % 16 == 4 for h in hists)
+    args = list(b.descs_args)
+    args[2] = [h.data_ptr() for h in hists]
+    pixels = int((b.Hs.astype(np.int64) * b.Ws).sum())
+    plan = lib.BatchPlan(n, pixels, 3, cells[0], cells[1])
+    plan.set(lib.BatchPlan.descs(*args))
+    plan.run()
+    torch.cuda.synchronize()
+    for j in range(n):
+        _, want = oracle_c.ldp_extract(b.image(j), 3, *cells)
+        assert (hists[j].cpu().numpy().view(np.uint32).reshape(want.shape) == want).all(), j
+    plan.close()
+    for img in (b.image(0), synth.workload_image("single", 0)):
+        hv = torch.full((per + 4,), 7, dtype=torch.int32, device="cuda")[1:1 + per].view(7, 6, 256)
+        _, h = lib.extract(torch.from_numpy(np.ascontiguousarray(img)).cuda(), 3, *cells,
+                           hist_out=hv)
+        _, want = oracle_c.ldp_extract(img, 3, *cells)
+        assert (h.cpu().numpy().view(np.uint32) == want).all()
+
+
 @pytest.mark.parametrize("tune", [
     dict(block_threads=256), dict(block_threads=1024, classes=[dict(rows_per_task=16)]),
     dict(block_threads=512, classes=[dict(cell_rows_per_item=3)]),
