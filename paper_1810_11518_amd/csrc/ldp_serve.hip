@@ -22,6 +22,8 @@
 #include <thread>
 #include <vector>
 
+#include <sys/prctl.h>
+
 #include "ldp_host.hpp"
 
 namespace {
@@ -121,6 +123,14 @@ struct ldp_server {
 
 namespace {
 
+#ifndef LDP_SERVE_THREADS
+#define LDP_SERVE_THREADS 1024
+#endif
+// Launch shape of the server's plans, for latency: batches are a few images,
+// so each image is spread over many short lane tasks (one cell row per work
+// item, row bands of >= 4 rows, large workgroups) rather than few long ones.
+const ldp_tune kServeTune = {LDP_SERVE_THREADS, 0, 1, 0, {{INT64_MAX, 1, 4}}};
+
 // Device work of one batch on its stream; returns a status.
 int launch_batch(ldp_server *s, Batch &b)
 {
@@ -174,6 +184,9 @@ bool batch_finished(ldp_server *s, Batch &b, double t)
 
 void dispatcher(ldp_server *s)
 {
+    // timed waits of this thread end within ~1 us of their deadline instead
+    // of the default 50 us timer slack (the completion polls below are 20 us)
+    (void)prctl(PR_SET_TIMERSLACK, 1000UL, 0UL, 0UL, 0UL);
     if (!s->cfg.dry_run)
         (void)hipSetDevice(s->device);
     std::unique_lock<std::mutex> lk(s->mu);
@@ -243,13 +256,12 @@ void dispatcher(ldp_server *s)
         if (s->stop && s->pending.empty() && s->inflight.empty())
             break;
         if (!progressed) {
+            // idle: wait for a submission; batches in flight: poll their
+            // events every 20 us, and wake at once for a submission
             if (s->inflight.empty())
                 s->cv_work.wait_for(lk, std::chrono::milliseconds(2));
-            else {
-                lk.unlock();
-                std::this_thread::sleep_for(std::chrono::microseconds(20));
-                lk.lock();
-            }
+            else
+                s->cv_work.wait_for(lk, std::chrono::microseconds(20));
         }
     }
 }
@@ -319,7 +331,7 @@ int ldp_server_create(ldp_server **out, const ldp_server_config *cfg)
             s->streams.push_back(st);
             s->events.push_back(ev);
             int rc = ldp_batch_plan_create(&p, c.max_batch, c.pool_bytes, c.k, c.cells_y,
-                                           c.cells_x, nullptr);
+                                           c.cells_x, &kServeTune);
             if (rc != LDP_OK) {
                 release_server(s);
                 return rc;
