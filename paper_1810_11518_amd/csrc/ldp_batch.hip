@@ -137,6 +137,14 @@ struct ldp_batch_plan {
     ldp_size_class classes[LDP_MAX_SIZE_CLASSES] = {{INT64_MAX, 1, 8}};
     size_t lds_bytes = 0;
     int device = 0;
+    // One device block and its pinned staging mirror, laid out as
+    // [meta | descriptors | work items], so that a batch uploads in one copy.
+    // A window plan whose batch needs more items than the block holds moves
+    // its item table to allocations of its own (the kernel reads the table's
+    // address from the meta words).
+    char *d_block = nullptr, *h_block = nullptr;
+    size_t descs_off = 0, items_off = 0;
+    bool items_in_block = true;
     ldp_image_desc *d_descs = nullptr;
     ldp::Item *d_items = nullptr;
     ldp::Meta *d_meta = nullptr;
@@ -161,12 +169,12 @@ void release(ldp_batch_plan *p)
     if (p->graph) (void)hipGraphDestroy(p->graph);
     if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
     if (p->uploaded) (void)hipEventDestroy(p->uploaded);
-    if (p->d_descs) (void)hipFree(p->d_descs);
-    if (p->d_items) (void)hipFree(p->d_items);
-    if (p->d_meta) (void)hipFree(p->d_meta);
-    if (p->h_descs) (void)hipHostFree(p->h_descs);
-    if (p->h_items) (void)hipHostFree(p->h_items);
-    if (p->h_meta) (void)hipHostFree(p->h_meta);
+    if (!p->items_in_block) {
+        if (p->d_items) (void)hipFree(p->d_items);
+        if (p->h_items) (void)hipHostFree(p->h_items);
+    }
+    if (p->d_block) (void)hipFree(p->d_block);
+    if (p->h_block) (void)hipHostFree(p->h_block);
     delete p;
 }
 
@@ -253,13 +261,19 @@ int create_plan(ldp_batch_plan **out, int32_t max_images, int64_t max_pixels, in
         release(p);
         return st;
     };
-    if (hipMalloc(&p->d_descs, sizeof(ldp_image_desc) * max_images) != hipSuccess ||
-        hipMalloc(&p->d_items, sizeof(ldp::Item) * p->max_items) != hipSuccess ||
-        hipMalloc(&p->d_meta, sizeof(ldp::Meta)) != hipSuccess ||
-        hipHostMalloc(&p->h_descs, sizeof(ldp_image_desc) * max_images) != hipSuccess ||
-        hipHostMalloc(&p->h_items, sizeof(ldp::Item) * p->max_items) != hipSuccess ||
-        hipHostMalloc(&p->h_meta, sizeof(ldp::Meta)) != hipSuccess)
+    auto round256 = [](size_t n) { return (n + 255) & ~(size_t)255; };
+    p->descs_off = round256(sizeof(ldp::Meta));
+    p->items_off = p->descs_off + round256(sizeof(ldp_image_desc) * (size_t)max_images);
+    const size_t block = p->items_off + sizeof(ldp::Item) * (size_t)p->max_items;
+    if (hipMalloc(&p->d_block, block) != hipSuccess ||
+        hipHostMalloc(&p->h_block, block) != hipSuccess)
         return fail(LDP_ERR_NO_MEMORY);
+    p->d_meta = reinterpret_cast<ldp::Meta *>(p->d_block);
+    p->d_descs = reinterpret_cast<ldp_image_desc *>(p->d_block + p->descs_off);
+    p->d_items = reinterpret_cast<ldp::Item *>(p->d_block + p->items_off);
+    p->h_meta = reinterpret_cast<ldp::Meta *>(p->h_block);
+    p->h_descs = reinterpret_cast<ldp_image_desc *>(p->h_block + p->descs_off);
+    p->h_items = reinterpret_cast<ldp::Item *>(p->h_block + p->items_off);
     if (hipMemset(p->d_meta, 0, sizeof(ldp::Meta)) != hipSuccess)
         return fail(LDP_ERR_HIP);
 
@@ -397,8 +411,11 @@ int ldp_batch_plan_set(ldp_batch_plan *p, const ldp_image_desc *descs, int32_t n
             (void)hipHostFree(h);
             return LDP_ERR_HIP;
         }
-        (void)hipFree(p->d_items);
-        (void)hipHostFree(p->h_items);
+        if (!p->items_in_block) {
+            (void)hipFree(p->d_items);
+            (void)hipHostFree(p->h_items);
+        }
+        p->items_in_block = false;
         p->d_items = d;
         p->h_items = h;
         p->max_items = cap;
@@ -415,12 +432,15 @@ int ldp_batch_plan_set(ldp_batch_plan *p, const ldp_image_desc *descs, int32_t n
     p->h_meta->next = 0;
     p->h_meta->items = p->d_items;
     hipStream_t s = (hipStream_t)stream;
-    if (hipMemcpyAsync(p->d_descs, p->h_descs, sizeof(ldp_image_desc) * n, hipMemcpyHostToDevice,
-                       s) != hipSuccess ||
-        hipMemcpyAsync(p->d_items, p->h_items, sizeof(ldp::Item) * p->n_items,
-                       hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(p->d_meta, p->h_meta, sizeof(ldp::Meta), hipMemcpyHostToDevice, s) !=
-            hipSuccess ||
+    // meta and descriptors (and the items while they are in the block) in
+    // one copy
+    const size_t head = p->items_in_block
+                            ? p->items_off + sizeof(ldp::Item) * (size_t)p->n_items
+                            : p->descs_off + sizeof(ldp_image_desc) * (size_t)n;
+    if (hipMemcpyAsync(p->d_block, p->h_block, head, hipMemcpyHostToDevice, s) != hipSuccess ||
+        (!p->items_in_block && p->n_items > 0 &&
+         hipMemcpyAsync(p->d_items, p->h_items, sizeof(ldp::Item) * p->n_items,
+                        hipMemcpyHostToDevice, s) != hipSuccess) ||
         hipEventRecord(p->uploaded, s) != hipSuccess)
         return LDP_ERR_HIP;
     return LDP_OK;
