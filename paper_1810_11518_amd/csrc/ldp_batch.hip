@@ -29,12 +29,14 @@ struct Item {
 // Device meta words of a plan: [0] item count, [1] queue counter, [2..3] the
 // item table's address (the table can grow when a new batch is loaded
 // without re-capturing the graph).
+// The queue of a launch: item count, next item number, workgroups that found
+// the queue empty, item table.  The last workgroup to find it empty resets
+// `next` and `exited` to 0, so a replay of the same batch starts a fresh queue
+// (a new batch uploads zeros with its tables).
 struct Meta {
-    uint32_t n_items, next;
+    uint32_t n_items, next, exited, unused;
     const Item *items;
 };
-
-__global__ void clear_counter_kernel(Meta *meta) { meta->next = 0; }
 
 // At least 5 waves per SIMD: at most 96 VGPRs (allocated in steps of 8), the
 // occupancy the batch kernel is tuned for (4 waves measure ~17% slower).
@@ -93,6 +95,13 @@ __global__ void __launch_bounds__(1024) LDP_BATCH_ATTR batch_kernel(const ldp_im
         const int32_t r1 = geom_row_start(geo, w.cy1, im.Hc);
         // a null code pointer gives an empty store range: stores are dropped
         fused_item<K, MODE, true>(im, lds, geo, w.cy0, w.cy1, r0, r1, hist, false, w.min_rows);
+    }
+    // Every workgroup has taken its last number once all have counted
+    // themselves here: the last one resets the queue for the next launch
+    // (atomics: device-scope, through L2).
+    if (threadIdx.x == 0 && atomicAdd(&meta->exited, 1u) == gridDim.x - 1) {
+        atomicExch(&meta->next, 0u);
+        atomicExch(&meta->exited, 0u);
     }
 }
 
@@ -290,10 +299,10 @@ int create_plan(ldp_batch_plan **out, int32_t max_images, int64_t max_pixels, in
     if (hipStreamCreate(&p->cap_stream) != hipSuccess ||
         hipEventCreateWithFlags(&p->uploaded, hipEventDisableTiming) != hipSuccess)
         return fail(LDP_ERR_HIP);
-    // capture: clear the queue counter, then the persistent kernel
+    // capture: the persistent kernel (it leaves its queue reset for the next
+    // launch)
     if (hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return fail(LDP_ERR_HIP);
-    hipLaunchKernelGGL(ldp::clear_counter_kernel, dim3(1), dim3(1), 0, p->cap_stream, p->d_meta);
     hipLaunchKernelGGL(fn, dim3(p->grid), dim3(p->threads), p->lds_bytes, p->cap_stream,
                        (const ldp_image_desc *)p->d_descs, p->d_meta, gy, gx, windows ? 1 : 0,
                        (int32_t)(hist_bytes / 4));
@@ -430,6 +439,7 @@ int ldp_batch_plan_set(ldp_batch_plan *p, const ldp_image_desc *descs, int32_t n
     p->n_items = (int64_t)items.size();
     p->h_meta->n_items = (uint32_t)p->n_items;
     p->h_meta->next = 0;
+    p->h_meta->exited = 0;
     p->h_meta->items = p->d_items;
     hipStream_t s = (hipStream_t)stream;
     // meta and descriptors (and the items while they are in the block) in

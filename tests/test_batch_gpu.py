@@ -151,11 +151,19 @@ def test_graph_replay_with_new_batch_and_determinism(lib):
     for j in range(35):
         b2.check(j, 3, (4, 4))
     plan.set(lib.BatchPlan.descs(*b1.descs_args))
-    for _ in range(3):
+    # replays without a new set(): the kernel leaves its work queue reset, so
+    # every replay recomputes every image (outputs poisoned in between)
+    for rep in range(3):
+        for h in b1.hist:
+            h.fill_(7)
+        for c in b1.codes:
+            c.fill_(0xAB)
         plan.run()
-    torch.cuda.synchronize()
-    for j in range(20):
-        assert torch.equal(first[j], b1.hist[j])
+        torch.cuda.synchronize()
+        for j in range(20):
+            assert torch.equal(first[j], b1.hist[j]), (rep, j)
+        b1.check(0, 3, (4, 4))
+        b1.check(19, 3, (4, 4))
 
 
 def test_histograms_only_batch(lib):
