@@ -86,6 +86,10 @@ struct Req {
     int64_t stride;
     uint8_t *codes;
     uint32_t *hist;
+    // hist's device address when it is pinned host memory the GPU can write:
+    // the kernel then writes the histograms there itself (no device copy and
+    // no copy back); null otherwise
+    uint32_t *hist_dev = nullptr;
     double t_submit, t_admit = 0;
     int64_t off = -1, bytes = 0, img_bytes = 0, code_bytes = 0;
 };
@@ -142,7 +146,9 @@ int launch_batch(ldp_server *s, Batch &b)
     for (Req *r : b.reqs) {
         uint8_t *dimg = s->d_pool + r->off;
         uint8_t *dcodes = r->codes ? dimg + r->img_bytes : nullptr;
-        uint32_t *dhist = reinterpret_cast<uint32_t *>(dimg + r->img_bytes + r->code_bytes);
+        uint32_t *dhist = r->hist_dev ? r->hist_dev
+                                      : reinterpret_cast<uint32_t *>(dimg + r->img_bytes +
+                                                                     r->code_bytes);
         const hipError_t e =
             r->stride == r->W
                 ? hipMemcpyAsync(dimg, r->img, (size_t)r->H * r->W, hipMemcpyHostToDevice, st)
@@ -160,8 +166,9 @@ int launch_batch(ldp_server *s, Batch &b)
         return rc;
     for (size_t i = 0; i < b.reqs.size(); ++i) {
         Req *r = b.reqs[i];
-        if (hipMemcpyAsync(r->hist, descs[i].hist, s->hist_bytes, hipMemcpyDeviceToHost, st) !=
-            hipSuccess)
+        if (!r->hist_dev &&
+            hipMemcpyAsync(r->hist, descs[i].hist, s->hist_bytes, hipMemcpyDeviceToHost, st) !=
+                hipSuccess)
             return LDP_ERR_HIP;
         if (r->codes && hipMemcpyAsync(r->codes, descs[i].codes, (size_t)(r->H - 2) * (r->W - 2),
                                        hipMemcpyDeviceToHost, st) != hipSuccess)
@@ -387,9 +394,21 @@ int ldp_server_submit(ldp_server *s, const uint8_t *img, int32_t H, int32_t W, i
     r->stride = stride;
     r->codes = codes;
     r->hist = hist;
+    if (!s->cfg.dry_run) {
+        // pinned host memory mapped for the GPU at its host address (unified
+        // addressing): the kernel writes the histograms to `hist` itself
+        hipPointerAttribute_t at{};
+        if (hipPointerGetAttributes(&at, hist) == hipSuccess) {
+            if (at.type == hipMemoryTypeHost && at.devicePointer != nullptr &&
+                at.devicePointer == at.hostPointer)
+                r->hist_dev = hist;
+        } else {
+            (void)hipGetLastError();  // leave no error from the query for the caller's next call
+        }
+    }
     r->img_bytes = round256((int64_t)H * W);
     r->code_bytes = codes ? round256((int64_t)(H - 2) * (W - 2)) : 0;
-    r->bytes = r->img_bytes + r->code_bytes + round256(s->hist_bytes);
+    r->bytes = r->img_bytes + r->code_bytes + (r->hist_dev ? 0 : round256(s->hist_bytes));
     std::lock_guard<std::mutex> lk(s->mu);
     if (r->bytes > s->pool->size()) {
         s->st.rejected += 1;

@@ -123,3 +123,28 @@ def test_histograms_only_requests(lib):
     srv.close()
     for (keep, img), (k, hist) in zip(reqs, hists):
         assert (hist.reshape(7, 6, 256) == oracle_c.ldp_extract(img, 3, 7, 6)[1]).all()
+
+
+def test_pageable_buffers_take_the_copy_path(lib):
+    """Plain (pageable) host buffers: the server copies images in and results
+    out (pinned outputs are written by the kernel directly); same results."""
+    r = np.random.default_rng(17)
+    srv = lib.Server(1 << 28, max_inflight=64, max_batch=16, depth=2, k=3, cells_y=7, cells_x=6)
+    keep = []
+    for j in range(12):
+        H, W = int(r.integers(12, 400)), int(r.integers(12, 500))
+        img = synth.image(synth.KIND_BLUR_RECTS, 19, j, H, W)
+        codes = np.full((H - 2) * (W - 2), 0xAB, np.uint8)
+        hist = np.full(7 * 6 * 256, 7, np.uint32)
+        if j % 2:
+            kh, hist = _pinned((7 * 6 * 256,), np.uint32)   # mixed in one batch
+            hist[:] = 7
+            keep.append(kh)
+        srv.submit(img, hist, codes)
+        keep.append((img, codes, hist))
+    _drain(srv, 12)
+    srv.close()
+    for img, codes, hist in [x for x in keep if isinstance(x, tuple)]:
+        want_c, want_h = oracle_c.ldp_extract(img, 3, 7, 6)
+        assert (codes.reshape(want_c.shape) == want_c).all()
+        assert (hist.reshape(want_h.shape) == want_h).all()
