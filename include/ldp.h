@@ -337,8 +337,9 @@ int ldp_server_create(ldp_server **server, const ldp_server_config *config);
  * ((H-2)*(W-2) bytes, may be NULL) and hist (cells_y*cells_x*256 uint32) are
  * HOST outputs written before the request completes.  All three buffers must
  * stay valid until completion; page-locked memory gives asynchronous copies,
- * and a page-locked hist that the GPU addresses at its host address is
- * written by the kernel directly (no device copy, no copy back).  Returns the
+ * and page-locked img and hist buffers that the GPU addresses at their host
+ * addresses are read and written by the kernel in place (no copy in, no
+ * device copy of the histograms, no copy back).  Returns the
  * request id in *id.  Errors: LDP_ERR_INVALID_ARG (bad sizes),
  * LDP_ERR_NO_MEMORY (the request can never fit the pool: rejected). */
 int ldp_server_submit(ldp_server *server, const uint8_t *img, int32_t H, int32_t W,

@@ -90,6 +90,8 @@ struct Req {
     // the kernel then writes the histograms there itself (no device copy and
     // no copy back); null otherwise
     uint32_t *hist_dev = nullptr;
+    // the same for the image: the kernel reads it in place (no copy in)
+    const uint8_t *img_dev = nullptr;
     double t_submit, t_admit = 0;
     int64_t off = -1, bytes = 0, img_bytes = 0, code_bytes = 0;
 };
@@ -149,6 +151,10 @@ int launch_batch(ldp_server *s, Batch &b)
         uint32_t *dhist = r->hist_dev ? r->hist_dev
                                       : reinterpret_cast<uint32_t *>(dimg + r->img_bytes +
                                                                      r->code_bytes);
+        if (r->img_dev) {
+            descs.push_back({r->img_dev, dcodes, dhist, r->stride, r->H, r->W});
+            continue;
+        }
         const hipError_t e =
             r->stride == r->W
                 ? hipMemcpyAsync(dimg, r->img, (size_t)r->H * r->W, hipMemcpyHostToDevice, st)
@@ -208,7 +214,8 @@ void dispatcher(ldp_server *s)
                 continue;
             }
             for (Req *r : b.reqs) {
-                s->pool->release(r->off, r->bytes);
+                if (r->bytes)
+                    s->pool->release(r->off, r->bytes);
                 s->done.push_back({r->id, r->t_submit, r->t_admit, t, b.status,
                                    (int32_t)b.reqs.size()});
                 delete r;
@@ -234,7 +241,9 @@ void dispatcher(ldp_server *s)
             while (!s->pending.empty() && (int)b.reqs.size() < s->cfg.max_batch &&
                    s->inflight_reqs + (int)b.reqs.size() < s->cfg.max_inflight) {
                 Req *r = s->pending.front();
-                const int64_t off = s->pool->alloc(r->bytes);
+                // requests whose buffers are all read and written in place
+                // need no pool space
+                const int64_t off = r->bytes ? s->pool->alloc(r->bytes) : 0;
                 if (off < 0)
                     break;  // head of line waits for memory
                 r->off = off;
@@ -405,8 +414,19 @@ int ldp_server_submit(ldp_server *s, const uint8_t *img, int32_t H, int32_t W, i
         } else {
             (void)hipGetLastError();  // leave no error from the query for the caller's next call
         }
+        // and the image: read in place by the kernel, with its own pitch
+        // (when that extent fits the kernel's 32-bit offsets)
+        hipPointerAttribute_t ai{};
+        if (hipPointerGetAttributes(&ai, img) == hipSuccess) {
+            if (ai.type == hipMemoryTypeHost && ai.devicePointer != nullptr &&
+                ai.devicePointer == ai.hostPointer &&
+                (int64_t)(H - 1) * stride + W + 8 <= ldp::kMaxExtent)
+                r->img_dev = img;
+        } else {
+            (void)hipGetLastError();
+        }
     }
-    r->img_bytes = round256((int64_t)H * W);
+    r->img_bytes = r->img_dev ? 0 : round256((int64_t)H * W);
     r->code_bytes = codes ? round256((int64_t)(H - 2) * (W - 2)) : 0;
     r->bytes = r->img_bytes + r->code_bytes + (r->hist_dev ? 0 : round256(s->hist_bytes));
     std::lock_guard<std::mutex> lk(s->mu);

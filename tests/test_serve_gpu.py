@@ -127,13 +127,19 @@ def test_histograms_only_requests(lib):
 
 def test_pageable_buffers_take_the_copy_path(lib):
     """Plain (pageable) host buffers: the server copies images in and results
-    out (pinned outputs are written by the kernel directly); same results."""
+    out (pinned images and histograms are read and written by the kernel in
+    place, here also pinned images with padded rows); same results."""
     r = np.random.default_rng(17)
     srv = lib.Server(1 << 28, max_inflight=64, max_batch=16, depth=2, k=3, cells_y=7, cells_x=6)
     keep = []
     for j in range(12):
         H, W = int(r.integers(12, 400)), int(r.integers(12, 500))
         img = synth.image(synth.KIND_BLUR_RECTS, 19, j, H, W)
+        if j % 3 == 2:
+            kp, padded = _pinned((H, W + 5), np.uint8)   # pinned, pitch W + 5
+            padded[:, :W] = img
+            img = padded[:, :W]
+            keep.append(kp)
         codes = np.full((H - 2) * (W - 2), 0xAB, np.uint8)
         hist = np.full(7 * 6 * 256, 7, np.uint32)
         if j % 2:
