@@ -198,7 +198,7 @@ bool batch_finished(ldp_server *s, Batch &b, double t)
 void dispatcher(ldp_server *s)
 {
     // timed waits of this thread end within ~1 us of their deadline instead
-    // of the default 50 us timer slack (the completion polls below are 20 us)
+    // of the default 50 us timer slack (the completion polls below are 5 us)
     (void)prctl(PR_SET_TIMERSLACK, 1000UL, 0UL, 0UL, 0UL);
     if (!s->cfg.dry_run)
         (void)hipSetDevice(s->device);
@@ -273,11 +273,11 @@ void dispatcher(ldp_server *s)
             break;
         if (!progressed) {
             // idle: wait for a submission; batches in flight: poll their
-            // events every 20 us, and wake at once for a submission
+            // events every 5 us, and wake at once for a submission
             if (s->inflight.empty())
                 s->cv_work.wait_for(lk, std::chrono::milliseconds(2));
             else
-                s->cv_work.wait_for(lk, std::chrono::microseconds(20));
+                s->cv_work.wait_for(lk, std::chrono::microseconds(5));
         }
     }
 }
