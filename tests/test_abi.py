@@ -56,6 +56,13 @@ def test_invalid_arguments_return_before_any_launch(lib):
     assert lib.ldp_extract(p, 10, 10, 10, 3, 1, 1, None, None, None) == E
     assert lib.ldp_extract(p, 10, 10, 10, 3, 0, 1, p, p, None) == E
     assert lib.ldp_codes(p, 40000, 60000, 60000, 3, p, None) == binding.LDP_ERR_UNSUPPORTED
+    # sides above 65536, and the first extents past (H - 1) * stride + W + 8 <= 2^31 - 64
+    # (32767 x 65536 at pitch 65536, the largest image the GPU tests run, is inside)
+    assert lib.ldp_codes(p, 10, 65537, 65537, 3, p, None) == E
+    assert lib.ldp_codes(p, 65537, 10, 10, 3, p, None) == E
+    assert lib.ldp_codes(p, 32768, 65536, 65536, 3, p, None) == binding.LDP_ERR_UNSUPPORTED
+    assert lib.ldp_codes(p, 32767, 65536, 65538, 3, p, None) == binding.LDP_ERR_UNSUPPORTED
+    assert lib.ldp_extract(p, 32768, 65536, 65536, 3, 16, 16, p, p, None) == binding.LDP_ERR_UNSUPPORTED
     plan = ctypes.c_void_p()
     assert lib.ldp_batch_plan_create(ctypes.byref(plan), 0, 100, 3, 7, 6, None) == E
     assert lib.ldp_batch_plan_create(ctypes.byref(plan), 10, 100, 9, 7, 6, None) == E
