@@ -74,7 +74,7 @@ def parse():
     ap.add_argument("--variant-steps", type=int, default=20,
                     help="timed launches of each variant path (magnitude ranking, Eq. 6 compact "
                          "histograms) on the same batch; 0 skips them")
-    ap.add_argument("--serve-rates", default="2000,10000",
+    ap.add_argument("--serve-rates", default="1000,2000,10000,50000",
                     help="comma-separated Poisson arrival rates (images/s) for the serving "
                          "run; empty to skip")
     ap.add_argument("--serve-seconds", type=float, default=1.5)
