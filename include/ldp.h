@@ -263,6 +263,23 @@ int ldp_batch_plan_set(ldp_batch_plan *plan, const ldp_image_desc *descs, int32_
 /* ldp_batch_run -- run the loaded batch on `stream` (one graph launch). */
 int ldp_batch_run(ldp_batch_plan *plan, ldp_stream_t stream);
 
+/*
+ * ldp_batch_launch -- load and run a batch in one call: the results of
+ * ldp_batch_plan_set followed by ldp_batch_run, with the same checks and
+ * errors.  On a plan with cells (not windows) and flags 0, a batch of at most
+ * LDP_ARG_BATCH_IMAGES images and LDP_ARG_BATCH_ITEMS work items (see
+ * ldp_batch_plan_info) travels in the kernel launch's own arguments: no table
+ * upload and no graph launch, and the plan's loaded batch (what
+ * ldp_batch_run runs) stays as it was.  Any other batch is loaded with
+ * ldp_batch_plan_set (it becomes the loaded batch) and run.  Launches on one
+ * plan share its work queue: order them (one stream, or events across
+ * streams), as for ldp_batch_run.
+ */
+#define LDP_ARG_BATCH_IMAGES 28
+#define LDP_ARG_BATCH_ITEMS 196
+int ldp_batch_launch(ldp_batch_plan *plan, const ldp_image_desc *descs, int32_t n,
+                     ldp_stream_t stream);
+
 /* ldp_batch_run_per_image -- the same batch as one ldp_extract launch per
  * image, for comparison with the persistent launch. */
 int ldp_batch_run_per_image(ldp_batch_plan *plan, ldp_stream_t stream);
@@ -280,8 +297,9 @@ int ldp_batch_plan_destroy(ldp_batch_plan *plan);
  * HOST result buffers) is admitted when the server's device memory pool has
  * room for its image, codes and histograms and a request slot is free;
  * otherwise it waits, in arrival order.  A dispatcher thread copies admitted
- * images to the device and launches them as one persistent batch (the
- * descriptor and work tables and the work queue live on the device) on one
+ * images to the device and launches them as one persistent batch
+ * (ldp_batch_launch: a small batch's tables travel in the launch arguments,
+ * a larger one's are uploaded; the work queue lives on the device) on one
  * of `depth` streams, so requests that arrive while earlier batches run are
  * admitted as memory frees up and their work overlaps on the device.  When a
  * batch's results are back on the host its memory and slots are released.
@@ -327,9 +345,10 @@ double ldp_now(void);
 
 /* Create a server (allocates the pool, streams and batch plans; starts the
  * dispatcher thread).  Without dry_run it also launches every slot's batch
- * graph once on an empty batch and runs one small copy of each kind on the
- * slot's stream, synchronously, so that one-time runtime set-up does not
- * fall on the first requests (a few milliseconds at creation).  Errors:
+ * kernels (graph and argument-table forms) once on an empty batch and runs
+ * one small copy of each kind on the slot's stream, synchronously, so that
+ * one-time runtime set-up does not fall on the first requests (a few
+ * milliseconds at creation).  Errors:
  * LDP_ERR_INVALID_ARG, LDP_ERR_NO_MEMORY, LDP_ERR_HIP. */
 int ldp_server_create(ldp_server **server, const ldp_server_config *config);
 

@@ -31,7 +31,7 @@ EXPORTED = [
     "ldp_codes_ex", "ldp_extract_ex", "ldp_compact_bins", "ldp_compact_histograms",
     "ldp_window_grid", "ldp_histograms_windows", "ldp_extract_windows",
     "ldp_batch_plan_create", "ldp_batch_plan_create_ex", "ldp_batch_plan_create_windows",
-    "ldp_batch_plan_set", "ldp_batch_run", "ldp_batch_run_per_image",
+    "ldp_batch_plan_set", "ldp_batch_run", "ldp_batch_launch", "ldp_batch_run_per_image",
     "ldp_batch_plan_info", "ldp_batch_plan_destroy",
     "ldp_now", "ldp_server_create", "ldp_server_submit", "ldp_server_poll",
     "ldp_server_stats_get", "ldp_server_destroy",
@@ -143,6 +143,7 @@ def load():
         "ldp_extract_windows": (ctypes.c_int, [p, i32, i32, i64, i32, i32, i32, i32, p, p, p]),
         "ldp_batch_plan_set": (ctypes.c_int, [p, ctypes.POINTER(ImageDesc), i32, p]),
         "ldp_batch_run": (ctypes.c_int, [p, p]),
+        "ldp_batch_launch": (ctypes.c_int, [p, ctypes.POINTER(ImageDesc), i32, p]),
         "ldp_batch_run_per_image": (ctypes.c_int, [p, p]),
         "ldp_batch_plan_info": (ctypes.c_int, [p, ctypes.POINTER(i64), ctypes.POINTER(i32)]),
         "ldp_batch_plan_destroy": (ctypes.c_int, [p]),
@@ -341,6 +342,12 @@ class BatchPlan:
 
     def run(self, stream=None):
         _check(self._lib.ldp_batch_run(self._plan, _stream(stream)), "ldp_batch_run")
+
+    def launch(self, descs, stream=None):
+        """Load and run `descs` in one call (ldp_batch_launch): small batches
+        travel in the launch's arguments and leave the loaded batch as it was."""
+        _check(self._lib.ldp_batch_launch(self._plan, descs, len(descs), _stream(stream)),
+               "ldp_batch_launch")
 
     def run_per_image(self, stream=None):
         _check(self._lib.ldp_batch_run_per_image(self._plan, _stream(stream)),

@@ -3,11 +3,13 @@
 // The host cuts every image into work items of whole cell rows, so each
 // item's histogram cells belong to exactly one workgroup and are written with
 // plain stores (no atomics, no zeroing pass).  Items are sorted largest
-// first and pulled by the resident workgroups from a device queue counter.
-// The launch (a one-thread kernel that clears the counter, then the
-// persistent kernel) is captured once in a HIP graph when the plan is made;
-// the kernels read the item count and tables from device memory, so loading
-// a new batch never re-captures the graph.
+// first and pulled by the resident workgroups from a device queue counter,
+// which the last workgroup to find the queue empty resets for the next
+// launch.  The persistent kernel is captured once in a HIP graph when the
+// plan is made; it reads the item count and tables from device memory, so
+// loading a new batch never re-captures the graph.  A batch small enough to
+// travel in the kernel's arguments can instead be launched directly with its
+// tables as arguments (no upload: `run_batch`).
 #include <stdint.h>
 
 #include <algorithm>
@@ -26,13 +28,12 @@ struct Item {
     int32_t min_rows;   // target code rows per lane task
 };
 
-// Device meta words of a plan: [0] item count, [1] queue counter, [2..3] the
-// item table's address (the table can grow when a new batch is loaded
-// without re-capturing the graph).
 // The queue of a launch: item count, next item number, workgroups that found
 // the queue empty, item table.  The last workgroup to find it empty resets
 // `next` and `exited` to 0, so a replay of the same batch starts a fresh queue
-// (a new batch uploads zeros with its tables).
+// (a new batch uploads zeros with its tables).  The item table's address is
+// read from here because a window plan's table can grow when a new batch is
+// loaded, without re-capturing the graph.
 struct Meta {
     uint32_t n_items, next, exited, unused;
     const Item *items;
@@ -52,24 +53,55 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v)
     return ((uint64_t)uniform((uint32_t)(v >> 32)) << 32) | uniform((uint32_t)v);
 }
 
+// Tables of a launch read from device memory (the graph launch).  The item
+// table does not change while a kernel runs: it is read through the constant
+// address space, so an item (and the descriptor it indexes) arrives in scalar
+// registers.
+struct DeviceTables {
+    const ConstItem *items;
+    const ldp_image_desc *descs;
+    __device__ __forceinline__ Item item(uint32_t i) const
+    {
+        const ConstItem &ci = items[i];
+        Item w;
+        w.img = ci.img;
+        w.cy0 = ci.cy0;
+        w.cy1 = ci.cy1;
+        w.min_rows = ci.min_rows;
+        return w;
+    }
+    __device__ __forceinline__ ldp_image_desc desc(int32_t j) const { return descs[j]; }
+};
+
+// A batch carried in the kernel's arguments: at most kArgImages images and
+// kArgItems work items (3,480 bytes of arguments).
+constexpr int32_t kArgImages = LDP_ARG_BATCH_IMAGES, kArgItems = LDP_ARG_BATCH_ITEMS;
+struct ArgBatch {
+    uint32_t n_items, unused;
+    ldp_image_desc descs[kArgImages];
+    Item items[kArgItems];
+};
+
+struct ArgTables {
+    const ArgBatch *b;  // the kernel's argument segment
+    __device__ __forceinline__ Item item(uint32_t i) const { return b->items[i]; }
+    __device__ __forceinline__ ldp_image_desc desc(int32_t j) const { return b->descs[j]; }
+};
+
+// The work of one workgroup: pull item numbers from the queue counter until
+// all n_items are taken, each item a fused pass over its cell rows.
 // (gy, gx): cells_y x cells_x cells, or with `windows` window sides in code
-// pixels (every image's cell grid follows from its own size).
-template <int K, int MODE>
-// The item number is broadcast through the LDS word after the histograms
-// (`item_slot`, in words): the kernel has no static LDS, and the histograms
-// start at the beginning of its dynamic LDS.
-__global__ void __launch_bounds__(1024) LDP_BATCH_ATTR batch_kernel(const ldp_image_desc *__restrict__ descs,
-                                                     Meta *meta, int32_t gy, int32_t gx,
-                                                     int32_t windows, int32_t item_slot)
+// pixels (every image's cell grid follows from its own size).  The item
+// number is broadcast through the LDS word after the histograms (`item_slot`,
+// in words): the kernels have no static LDS, and the histograms start at the
+// beginning of the dynamic LDS.
+template <int K, int MODE, class Tables>
+__device__ __forceinline__ void run_queue(const Tables &tab, uint32_t n_items, Meta *meta,
+                                          int32_t gy, int32_t gx, int32_t windows,
+                                          int32_t item_slot)
 {
     extern __shared__ uint32_t lds[];
     uint32_t &s_item = lds[item_slot];
-    // the item count and table address are the same for every lane:
-    // readfirstlane keeps them (and what is read through them) in scalar
-    // registers, which the buffer descriptors built from them must be in
-    const uint32_t n_items = uniform(meta->n_items);
-    const ConstItem *items =
-        (const ConstItem *)(uintptr_t)uniform64(reinterpret_cast<uint64_t>(meta->items));
     for (;;) {
         if (threadIdx.x == 0)
             s_item = atomicAdd(&meta->next, 1u);
@@ -78,16 +110,8 @@ __global__ void __launch_bounds__(1024) LDP_BATCH_ATTR batch_kernel(const ldp_im
         __syncthreads();
         if (it >= n_items)
             break;
-        // the item table does not change while the kernel runs: read through
-        // the constant address space, the item (and the descriptor it
-        // indexes) arrives in scalar registers
-        const ConstItem &ci = items[it];
-        Item w;
-        w.img = ci.img;
-        w.cy0 = ci.cy0;
-        w.cy1 = ci.cy1;
-        w.min_rows = ci.min_rows;
-        const ldp_image_desc d = descs[w.img];
+        const Item w = tab.item(it);
+        const ldp_image_desc d = tab.desc(w.img);
         uint32_t *hist = d.hist;
         ImgView im = make_view(d.img, d.stride, d.H, d.W, d.codes);
         const Geom geo = make_geom(im.Hc, im.Wc, gy, gx, windows != 0);
@@ -103,6 +127,47 @@ __global__ void __launch_bounds__(1024) LDP_BATCH_ATTR batch_kernel(const ldp_im
         atomicExch(&meta->next, 0u);
         atomicExch(&meta->exited, 0u);
     }
+}
+
+template <int K, int MODE>
+__global__ void __launch_bounds__(1024) LDP_BATCH_ATTR batch_kernel(const ldp_image_desc *__restrict__ descs,
+                                                     Meta *meta, int32_t gy, int32_t gx,
+                                                     int32_t windows, int32_t item_slot)
+{
+    // the item count and table address are the same for every lane:
+    // readfirstlane keeps them (and what is read through them) in scalar
+    // registers, which the buffer descriptors built from them must be in
+    const uint32_t n_items = uniform(meta->n_items);
+    const DeviceTables tab{
+        (const ConstItem *)(uintptr_t)uniform64(reinterpret_cast<uint64_t>(meta->items)), descs};
+    run_queue<K, MODE>(tab, n_items, meta, gy, gx, windows, item_slot);
+}
+
+// The same pass over a batch given in the arguments; only the queue counter
+// is read from device memory.
+template <int K, int MODE>
+__global__ void __launch_bounds__(1024) LDP_BATCH_ATTR batch_arg_kernel(const ArgBatch b, Meta *meta,
+                                                         int32_t gy, int32_t gx,
+                                                         int32_t windows, int32_t item_slot)
+{
+    run_queue<K, MODE>(ArgTables{&b}, b.n_items, meta, gy, gx, windows, item_slot);
+}
+
+typedef void (*batch_arg_fn)(const ArgBatch, Meta *, int32_t, int32_t, int32_t, int32_t);
+
+static batch_arg_fn batch_arg_kernel_for(int k)
+{
+    switch (k) {
+    case 1: return batch_arg_kernel<1, RANK_SIGNED>;
+    case 2: return batch_arg_kernel<2, RANK_SIGNED>;
+    case 3: return batch_arg_kernel<3, RANK_SIGNED>;
+    case 4: return batch_arg_kernel<4, RANK_SIGNED>;
+    case 5: return batch_arg_kernel<5, RANK_SIGNED>;
+    case 6: return batch_arg_kernel<6, RANK_SIGNED>;
+    case 7: return batch_arg_kernel<7, RANK_SIGNED>;
+    case 8: return batch_arg_kernel<8, RANK_SIGNED>;
+    }
+    return nullptr;
 }
 
 typedef void (*batch_fn)(const ldp_image_desc *, Meta *, int32_t, int32_t, int32_t, int32_t);
@@ -322,6 +387,63 @@ bool common_args_ok(ldp_batch_plan **out, int32_t max_images, int64_t max_pixels
 
 }  // namespace
 
+namespace {
+
+// Checks a batch against the plan and cuts it into work items (per image,
+// groups of its size class's cell rows), largest first.  Changes nothing.
+int cut_items(const ldp_batch_plan *p, const ldp_image_desc *descs, int32_t n,
+              std::vector<ldp::Item> &out)
+{
+    if (n > p->max_images)
+        return LDP_ERR_NO_MEMORY;
+    int64_t pixels = 0;
+    for (int32_t j = 0; j < n; ++j) {
+        const ldp_image_desc &d = descs[j];
+        int st = ldp::check_image(d.img, d.H, d.W, d.stride);
+        if (st != LDP_OK)
+            return st;
+        if (!d.hist)
+            return LDP_ERR_INVALID_ARG;
+        if (!p->windows && (d.H - 2 < p->gy || d.W - 2 < p->gx))
+            return LDP_ERR_INVALID_ARG;
+        if (p->windows && ldp::make_geom(d.H - 2, d.W - 2, p->gy, p->gx, true).nx > p->nx_max)
+            return LDP_ERR_INVALID_ARG;  // wider than the plan's max_width
+        pixels += (int64_t)d.H * d.W;
+    }
+    if (pixels > p->max_pixels)
+        return LDP_ERR_NO_MEMORY;
+    std::vector<ldp::Item> items;
+    std::vector<int64_t> size;
+    for (int32_t j = 0; j < n; ++j) {
+        const int64_t px = (int64_t)descs[j].H * descs[j].W;
+        int c = 0;
+        while (c < p->n_classes - 1 && px > p->classes[c].max_pixels)
+            ++c;
+        const int32_t cpi = p->classes[c].cell_rows_per_item;
+        const int32_t Hc = descs[j].H - 2;
+        const ldp::Geom geo = ldp::make_geom(Hc, descs[j].W - 2, p->gy, p->gx, p->windows);
+        for (int32_t cy = 0; cy < geo.ny; cy += cpi) {
+            const int32_t cy1 = std::min(cy + cpi, geo.ny);
+            items.push_back({j, (uint16_t)cy, (uint16_t)cy1, p->classes[c].rows_per_task});
+            const int64_t rows =
+                ldp::geom_row_start(geo, cy1, Hc) - ldp::geom_row_start(geo, cy, Hc);
+            size.push_back(rows * (descs[j].W - 2));
+        }
+    }
+    if ((int64_t)items.size() > p->max_items && !p->windows)
+        return LDP_ERR_NO_MEMORY;
+    std::vector<int64_t> order(items.size());
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int64_t a, int64_t b) { return size[a] > size[b]; });
+    out.resize(items.size());
+    for (size_t i = 0; i < order.size(); ++i)
+        out[i] = items[order[i]];
+    return LDP_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int ldp_batch_plan_create_ex(ldp_batch_plan **out, int32_t max_images, int64_t max_pixels,
@@ -360,50 +482,15 @@ int ldp_batch_plan_set(ldp_batch_plan *p, const ldp_image_desc *descs, int32_t n
 {
     if (!p || n < 0 || (n > 0 && !descs))
         return LDP_ERR_INVALID_ARG;
-    if (n > p->max_images)
-        return LDP_ERR_NO_MEMORY;
-    int64_t pixels = 0;
-    for (int32_t j = 0; j < n; ++j) {
-        const ldp_image_desc &d = descs[j];
-        int st = ldp::check_image(d.img, d.H, d.W, d.stride);
-        if (st != LDP_OK)
-            return st;
-        if (!d.hist)
-            return LDP_ERR_INVALID_ARG;
-        if (!p->windows && (d.H - 2 < p->gy || d.W - 2 < p->gx))
-            return LDP_ERR_INVALID_ARG;
-        if (p->windows && ldp::make_geom(d.H - 2, d.W - 2, p->gy, p->gx, true).nx > p->nx_max)
-            return LDP_ERR_INVALID_ARG;  // wider than the plan's max_width
-        pixels += (int64_t)d.H * d.W;
-    }
-    if (pixels > p->max_pixels)
-        return LDP_ERR_NO_MEMORY;
+    std::vector<ldp::Item> items;
+    int rc = cut_items(p, descs, n, items);
+    if (rc != LDP_OK)
+        return rc;
     // the staging buffers may still feed the previous upload
     if (hipEventSynchronize(p->uploaded) != hipSuccess)
         return LDP_ERR_HIP;
     p->descs.assign(descs, descs + n);
-    // work items: per image, groups of its size class's cell rows; largest first
-    std::vector<ldp::Item> items;
-    std::vector<int64_t> size;
-    for (int32_t j = 0; j < n; ++j) {
-        const int64_t px = (int64_t)descs[j].H * descs[j].W;
-        int c = 0;
-        while (c < p->n_classes - 1 && px > p->classes[c].max_pixels)
-            ++c;
-        const int32_t cpi = p->classes[c].cell_rows_per_item;
-        const int32_t Hc = descs[j].H - 2;
-        const ldp::Geom geo = ldp::make_geom(Hc, descs[j].W - 2, p->gy, p->gx, p->windows);
-        for (int32_t cy = 0; cy < geo.ny; cy += cpi) {
-            const int32_t cy1 = std::min(cy + cpi, geo.ny);
-            items.push_back({j, (uint16_t)cy, (uint16_t)cy1, p->classes[c].rows_per_task});
-            const int64_t rows =
-                ldp::geom_row_start(geo, cy1, Hc) - ldp::geom_row_start(geo, cy, Hc);
-            size.push_back(rows * (descs[j].W - 2));
-        }
-    }
     if ((int64_t)items.size() > p->max_items) {
-        if (!p->windows)
-            return LDP_ERR_NO_MEMORY;
         // window plans grow their item table (the graph reads its address
         // from the meta words, so nothing is re-captured)
         const int64_t cap = std::max<int64_t>((int64_t)items.size(), p->max_items * 3 / 2);
@@ -429,12 +516,7 @@ int ldp_batch_plan_set(ldp_batch_plan *p, const ldp_image_desc *descs, int32_t n
         p->h_items = h;
         p->max_items = cap;
     }
-    std::vector<int64_t> order(items.size());
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int64_t a, int64_t b) { return size[a] > size[b]; });
-    for (size_t i = 0; i < order.size(); ++i)
-        p->h_items[i] = items[order[i]];
+    std::copy(items.begin(), items.end(), p->h_items);
     std::copy(descs, descs + n, p->h_descs);
     p->n_items = (int64_t)items.size();
     p->h_meta->n_items = (uint32_t)p->n_items;
@@ -454,6 +536,12 @@ int ldp_batch_plan_set(ldp_batch_plan *p, const ldp_image_desc *descs, int32_t n
         hipEventRecord(p->uploaded, s) != hipSuccess)
         return LDP_ERR_HIP;
     return LDP_OK;
+}
+
+int ldp_batch_launch(ldp_batch_plan *p, const ldp_image_desc *descs, int32_t n,
+                     ldp_stream_t stream)
+{
+    return ldp::run_batch(p, descs, n, (hipStream_t)stream);
 }
 
 int ldp_batch_run(ldp_batch_plan *p, ldp_stream_t stream)
@@ -501,11 +589,69 @@ int ldp_batch_plan_destroy(ldp_batch_plan *p)
 }  // extern "C"
 
 namespace ldp {
+namespace {
+
+// The plan's kernel for batches in the launch arguments (nullptr when its
+// batches always go through the loaded tables: windows, or flags).
+batch_arg_fn arg_kernel(const ldp_batch_plan *p)
+{
+    return !p->windows && rank_mode(p->flags) == RANK_SIGNED ? batch_arg_kernel_for(p->k)
+                                                             : nullptr;
+}
+
+int launch_args(const ldp_batch_plan *p, batch_arg_fn fn, ArgBatch &b, hipStream_t s)
+{
+    // no more workgroups than items (at least one); the queue counter is zero
+    // between launches on this plan (each launch resets it)
+    const int32_t grid = (int32_t)std::max<int64_t>(1, std::min<int64_t>(p->grid, b.n_items));
+    Meta *meta = p->d_meta;
+    int32_t gy = p->gy, gx = p->gx, windows = 0;
+    int32_t item_slot = (int32_t)((p->lds_bytes - 16) / 4);
+    void *args[] = {&b, &meta, &gy, &gx, &windows, &item_slot};
+    return hipLaunchKernel(reinterpret_cast<const void *>(fn), dim3(grid), dim3(p->threads), args,
+                           p->lds_bytes, s) == hipSuccess
+               ? LDP_OK
+               : LDP_ERR_HIP;
+}
+
+}  // namespace
+
 int warm_plan(ldp_batch_plan *p, hipStream_t s)
 {
     int rc = ldp_batch_plan_set(p, nullptr, 0, (ldp_stream_t)s);
     if (rc != LDP_OK)
         return rc;
-    return hipGraphLaunch(p->exec, s) == hipSuccess ? LDP_OK : LDP_ERR_HIP;
+    if (hipGraphLaunch(p->exec, s) != hipSuccess)
+        return LDP_ERR_HIP;
+    // the argument-table kernel too: one workgroup that finds no work item
+    const batch_arg_fn fn = arg_kernel(p);
+    if (!fn)
+        return LDP_OK;
+    ArgBatch b{};
+    return launch_args(p, fn, b, s);
+}
+
+int run_batch(ldp_batch_plan *p, const ldp_image_desc *descs, int32_t n, hipStream_t s)
+{
+    if (!p || n < 0 || (n > 0 && !descs))
+        return LDP_ERR_INVALID_ARG;
+    const batch_arg_fn fn = n <= kArgImages ? arg_kernel(p) : nullptr;
+    if (fn) {
+        std::vector<Item> items;
+        int rc = cut_items(p, descs, n, items);
+        if (rc != LDP_OK)
+            return rc;
+        if (items.empty())
+            return LDP_OK;
+        if ((int64_t)items.size() <= kArgItems) {
+            ArgBatch b{};
+            b.n_items = (uint32_t)items.size();
+            std::copy(descs, descs + n, b.descs);
+            std::copy(items.begin(), items.end(), b.items);
+            return launch_args(p, fn, b, s);
+        }
+    }
+    int rc = ldp_batch_plan_set(p, descs, n, (ldp_stream_t)s);
+    return rc == LDP_OK ? ldp_batch_run(p, (ldp_stream_t)s) : rc;
 }
 }  // namespace ldp

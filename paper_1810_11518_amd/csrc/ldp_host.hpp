@@ -58,9 +58,18 @@ int launch_extract(const uint8_t *img, int32_t H, int32_t W, int64_t stride, int
                    uint32_t *hist, hipStream_t s);
 
 // Sets an empty batch on plan `p` and launches its graph on `s` anyway (its
-// workgroups find no work items and exit): the first launch on a stream
+// workgroups find no work items and exit), and likewise the kernel that
+// takes a batch in its arguments: the first launch of a kernel on a stream
 // pays one-time runtime set-up, which a server takes at creation instead of
 // on its first requests.
 int warm_plan(ldp_batch_plan *p, hipStream_t s);
+
+// ldp_batch_launch: runs batch `descs[0..n)` on plan `p` on stream `s`,
+// checked as ldp_batch_plan_set checks it.  A signed-ranking cell-grid batch
+// of at most LDP_ARG_BATCH_IMAGES images and LDP_ARG_BATCH_ITEMS work items
+// is launched with its tables in the kernel's arguments (no table upload, no
+// graph; the plan's loaded batch is left as it was); any other batch is
+// loaded with ldp_batch_plan_set and run.
+int run_batch(ldp_batch_plan *p, const ldp_image_desc *descs, int32_t n, hipStream_t s);
 
 }  // namespace ldp

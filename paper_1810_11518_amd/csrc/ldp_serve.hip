@@ -164,10 +164,7 @@ int launch_batch(ldp_server *s, Batch &b)
             return LDP_ERR_HIP;
         descs.push_back({dimg, dcodes, dhist, (int64_t)r->W, r->H, r->W});
     }
-    int rc = ldp_batch_plan_set(s->plans[b.slot], descs.data(), (int32_t)descs.size(),
-                                (ldp_stream_t)st);
-    if (rc == LDP_OK)
-        rc = ldp_batch_run(s->plans[b.slot], (ldp_stream_t)st);
+    int rc = ldp::run_batch(s->plans[b.slot], descs.data(), (int32_t)descs.size(), st);
     if (rc != LDP_OK)
         return rc;
     for (size_t i = 0; i < b.reqs.size(); ++i) {

@@ -196,3 +196,120 @@ def test_plan_rejects_bad_batches(lib):
     big = Batch([100] * 5, [100] * 5, synth.KIND_UNIFORM, 1, (7, 6))
     with pytest.raises(lib.LdpError):           # more images than the plan holds
         plan.set(lib.BatchPlan.descs(*big.descs_args))
+
+
+# ------------------------------------------------------------ ldp_batch_launch
+
+def _subset(lib, b, idx):
+    return lib.BatchPlan.descs(*[[x[j] for j in idx] for x in b.descs_args])
+
+
+def _poison(b):
+    for c in b.codes:
+        c.fill_(0xAB)
+    for h in b.hist:
+        h.fill_(7)
+
+
+def test_launch_small_batches_in_arguments_and_larger_ones_loaded(lib):
+    """One cell row per work item, 7 cell rows: 28 images are exactly the 196
+    items the launch arguments hold; 29 images and more are loaded into the
+    plan.  Launches interleave with runs of the loaded batch on one stream
+    (the two share the plan's work queue); the loaded batch changes only when
+    a launch loads one."""
+    r = np.random.default_rng(70)
+    n = 64
+    cells = (7, 6)
+    Hs, Ws = r.integers(9, 300, n), r.integers(8, 400, n)
+    Hs[:2], Ws[:2] = [490, 9], [640, 500]
+    b = Batch(Hs, Ws, synth.KIND_BLUR_SP_FLAT, 71, cells)
+    pixels = int((b.Hs.astype(np.int64) * b.Ws).sum())
+    plan = lib.BatchPlan(n, pixels, 3, *cells,
+                         tune=dict(block_threads=512, classes=[dict(cell_rows_per_item=1)]))
+    loaded = list(range(40, 64))
+    plan.set(_subset(lib, b, loaded))
+    for idx in ([0], list(range(1, 6)), list(range(6, 34)), list(range(0, 29)), [7, 3],
+                list(range(0, 40)), list(range(30, 58))):
+        _poison(b)
+        plan.launch(_subset(lib, b, idx))
+        if len(idx) > 28:
+            loaded = idx
+        plan.run()
+        torch.cuda.synchronize()
+        for j in sorted(set(idx) | set(loaded)):
+            b.check(j, 3, cells)
+        assert plan.info()[0] == 7 * len(loaded), idx
+    plan.launch(_subset(lib, b, []))  # nothing to do
+    plan.close()
+
+
+def test_launch_loads_batches_past_the_item_limit(lib):
+    """16 cell rows, one per item: 12 images (192 items) go in the arguments,
+    13 (208) are loaded."""
+    r = np.random.default_rng(72)
+    cells = (16, 6)
+    Hs, Ws = r.integers(18, 260, 13), r.integers(8, 300, 13)
+    b = Batch(Hs, Ws, synth.KIND_BLUR_RECTS, 73, cells)
+    pixels = int((b.Hs.astype(np.int64) * b.Ws).sum())
+    plan = lib.BatchPlan(13, pixels, 3, *cells, tune=dict(classes=[dict(cell_rows_per_item=1)]))
+    plan.set(_subset(lib, b, [0]))
+    _poison(b)
+    plan.launch(_subset(lib, b, list(range(12))))
+    torch.cuda.synchronize()
+    for j in range(12):
+        b.check(j, 3, cells)
+    assert plan.info()[0] == 16
+    _poison(b)
+    plan.launch(_subset(lib, b, list(range(13))))
+    torch.cuda.synchronize()
+    for j in range(13):
+        b.check(j, 3, cells)
+    assert plan.info()[0] == 16 * 13
+    plan.close()
+
+
+def test_launch_on_flagged_and_window_plans_loads_the_batch(lib):
+    from oracle import ldp as oracle_np
+    r = np.random.default_rng(74)
+    Hs, Ws = r.integers(12, 200, 5), r.integers(12, 300, 5)
+    b = Batch(Hs, Ws, synth.KIND_BLUR_SP_FLAT, 75, (7, 6))
+    pixels = int((b.Hs.astype(np.int64) * b.Ws).sum())
+    plan = lib.BatchPlan(5, pixels, 3, 7, 6, flags=lib.LDP_RANK_MAGNITUDE)
+    plan.launch(lib.BatchPlan.descs(*b.descs_args))
+    torch.cuda.synchronize()
+    assert plan.info()[0] == 5 * 7  # loaded: one cell row per item by default
+    for j in range(5):
+        wc, wh = oracle_c.ldp_extract(b.image(j), 3, 7, 6, magnitude=True)
+        assert (b.codes[j].cpu().numpy().reshape(wc.shape) == wc).all(), j
+        assert (b.hist[j].cpu().numpy().view(np.uint32).reshape(wh.shape) == wh).all(), j
+    plan.close()
+    win = (40, 50)
+    hists = [torch.full((-(-(int(h) - 2) // win[0]) * -(-(int(w) - 2) // win[1]) * 256,), 7,
+                        dtype=torch.int32, device="cuda") for h, w in zip(Hs, Ws)]
+    args = list(b.descs_args)
+    args[2] = [h.data_ptr() for h in hists]
+    plan = lib.BatchPlan(5, pixels, 3, *win, windows=True, max_width=300)
+    plan.launch(lib.BatchPlan.descs(*args))
+    torch.cuda.synchronize()
+    assert plan.info()[0] > 0
+    for j in range(5):
+        wc = oracle_c.ldp_codes(b.image(j), 3)
+        wh = oracle_np.window_histograms(wc, *win)
+        assert (hists[j].cpu().numpy().view(np.uint32) == wh.ravel()).all(), j
+    plan.close()
+
+
+def test_launch_rejects_a_bad_image_and_launches_nothing(lib):
+    r = np.random.default_rng(76)
+    Hs, Ws = r.integers(20, 100, 4), r.integers(20, 100, 4)
+    b = Batch(Hs, Ws, synth.KIND_BLUR_RECTS, 77, (7, 6))
+    pixels = int((b.Hs.astype(np.int64) * b.Ws).sum())
+    plan = lib.BatchPlan(4, pixels, 3, 7, 6)
+    args = [list(x) for x in b.descs_args]
+    args[4][2] = 8  # 6 code rows: fewer than the 7 cell rows
+    with pytest.raises(lib.LdpError):
+        plan.launch(lib.BatchPlan.descs(*args))
+    torch.cuda.synchronize()
+    assert all((h == 7).all() for h in b.hist)
+    assert plan.info()[0] == 0
+    plan.close()

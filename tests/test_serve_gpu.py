@@ -154,3 +154,39 @@ def test_pageable_buffers_take_the_copy_path(lib):
         want_c, want_h = oracle_c.ldp_extract(img, 3, 7, 6)
         assert (codes.reshape(want_c.shape) == want_c).all()
         assert (hist.reshape(want_h.shape) == want_h).all()
+
+
+def test_burst_behind_a_large_image_then_single_requests(lib):
+    """One slot: a large image holds it while 60 requests queue, so the next
+    batches are large (their tables are uploaded when they pass 28 images or
+    196 work items; 16 x 6 cells give 16 items per image); single requests
+    afterwards travel in the launch arguments.  Every histogram equals the
+    oracle's."""
+    cells = (16, 6)
+    srv = lib.Server(1 << 30, max_inflight=128, max_batch=64, depth=1, k=3, cells_y=cells[0],
+                     cells_x=cells[1])
+    r = np.random.default_rng(17)
+    shapes = [(3000, 3000)] + [(int(r.integers(20, 400)), int(r.integers(9, 500))) for _ in range(60)]
+    shapes += [(int(r.integers(20, 400)), int(r.integers(9, 500))) for _ in range(12)]
+    imgs, outs, keeps = [], [], []
+    for j, (H, W) in enumerate(shapes):
+        keep, img = _pinned((H, W), np.uint8)
+        img[:] = synth.image(synth.KIND_BLUR_SP_FLAT, 18, j, H, W)
+        kh, hist = _pinned((cells[0] * cells[1] * 256,), np.uint32)
+        hist[:] = 7
+        imgs.append(img)
+        outs.append(hist)
+        keeps += [keep, kh]
+    for j in range(61):                      # the large image, then a burst
+        srv.submit(imgs[j], outs[j])
+    done = _drain(srv, 61)
+    for j in range(61, len(shapes)):         # one at a time
+        srv.submit(imgs[j], outs[j])
+        done += _drain(srv, 1)
+    st = srv.stats()
+    srv.close()
+    assert all(d["status"] == 0 for d in done)
+    assert st["max_batch_seen"] > 1, st
+    for img, hist in zip(imgs, outs):
+        _, want = oracle_c.ldp_extract(img, 3, *cells)
+        assert (hist.reshape(want.shape) == want).all(), img.shape
