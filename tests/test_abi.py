@@ -71,6 +71,8 @@ def test_invalid_arguments_return_before_any_launch(lib):
         t = binding.make_tune(dict(block_threads=th))
         assert lib.ldp_batch_plan_create(ctypes.byref(plan), 10, 100, 3, 7, 6, ctypes.byref(t)) == E
     assert lib.ldp_batch_run(None, None) == E
+    assert lib.ldp_batch_launch(None, None, 0, None) == E
+    assert lib.ldp_batch_launch(None, None, -1, None) == E
     # variants: unknown flag bits, and the same checks as the plain calls
     for bad_flags in (3, 5, 6, 7, 8, -1):  # one flag at most, and only known ones
         assert lib.ldp_codes_ex(p, 10, 10, 10, 3, bad_flags, p, None) == E
