@@ -18,7 +18,11 @@
  * South-East; only interior pixels get codes, stored densely as
  * codes[(x-1)*(W-2) + (y-1)].
  *
- * Build: gcc -O2 -fPIC -shared -o liboracle_ldp.so ldp_oracle.c
+ * ldp_oracle_extract_batch runs the two per-image functions over many images,
+ * one image per OpenMP task: the arithmetic of every image is exactly that of
+ * the single-image calls, only several images are computed at once.
+ *
+ * Build: gcc -O2 -fopenmp -fPIC -shared -o liboracle_ldp.so ldp_oracle.c
  */
 #include <stdint.h>
 #include <string.h>
@@ -103,4 +107,38 @@ int ldp_oracle_histograms(const uint8_t *codes, int32_t H, int32_t W,
         }
     }
     return 0;
+}
+
+/* Codes and histograms of n images (each as ldp_oracle_codes_ex followed by
+ * ldp_oracle_histograms), images distributed over `threads` OpenMP threads
+ * (threads < 1: one).  Image j has Hs[j] rows of Ws[j] bytes with pitch
+ * strides[j], starting at base + img_off[j]; its codes go to
+ * codes + code_off[j] ((H-2)*(W-2) bytes) and its histograms to
+ * hist + j*cells_y*cells_x*256.  Returns 0, or -1 if any image's arguments are
+ * invalid (checked before any image is computed). */
+int ldp_oracle_extract_batch(const uint8_t *base, const int64_t *img_off, const int32_t *Hs,
+                             const int32_t *Ws, const int64_t *strides, int32_t n, int32_t k,
+                             int32_t flags, int32_t cells_y, int32_t cells_x, uint8_t *codes,
+                             const int64_t *code_off, uint32_t *hist, int32_t threads)
+{
+    if (n < 0 || (n > 0 && (!base || !img_off || !Hs || !Ws || !strides || !codes ||
+                            !code_off || !hist)))
+        return -1;
+    if (k < 1 || k > 8 || (flags & ~1) || cells_y < 1 || cells_x < 1)
+        return -1;
+    for (int32_t j = 0; j < n; ++j)
+        if (Hs[j] < 3 || Ws[j] < 3 || strides[j] < Ws[j] || cells_y > Hs[j] - 2 ||
+            cells_x > Ws[j] - 2)
+            return -1;
+    const int64_t per = (int64_t)cells_y * cells_x * 256;
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(threads < 1 ? 1 : threads) \
+    reduction(| : bad)
+    for (int32_t j = 0; j < n; ++j) {
+        bad |= ldp_oracle_codes_ex(base + img_off[j], Hs[j], Ws[j], strides[j], k, flags,
+                                   codes + code_off[j]) != 0;
+        bad |= ldp_oracle_histograms(codes + code_off[j], Hs[j], Ws[j], cells_y, cells_x,
+                                     hist + (int64_t)j * per) != 0;
+    }
+    return bad ? -1 : 0;
 }

@@ -340,3 +340,31 @@ def test_c_oracle_argument_checks(oracle_c):
         oracle_c.ldp_codes(np.zeros((9, 9), np.uint8), 9)
     with pytest.raises(ValueError):
         oracle_c.ldp_histograms(np.zeros((3, 3), np.uint8), 4, 1)
+
+
+def test_c_oracle_batch_equals_numpy_oracle_per_image(oracle_c):
+    """The threaded batch call computes every image as the numpy definition
+    does (strided rows, images of different sizes, any thread count)."""
+    r = _rng(15)
+    Hs = r.integers(3, 40, size=23).astype(np.int32)
+    Ws = r.integers(3, 40, size=23).astype(np.int32)
+    strides = Ws.astype(np.int64) + r.integers(0, 7, size=23)
+    off = np.concatenate([[0], np.cumsum(Hs * strides + 5)])[:-1]
+    buf = _rand_img(r, 1, int(off[-1] + Hs[-1] * strides[-1] + 8))[0]
+    for k, mag in ((3, False), (1, True), (8, False)):
+        want_c, want_h = [], []
+        for j in range(len(Hs)):
+            img = buf[off[j]:off[j] + Hs[j] * strides[j]].reshape(Hs[j], strides[j])[:, :Ws[j]]
+            c = ldp.ldp_codes(np.ascontiguousarray(img), k, magnitude=mag)
+            want_c.append(c.reshape(-1))
+            want_h.append(ldp.ldp_histograms(c, 1, 1))
+        for threads in (1, 4):
+            codes, coff, hist = oracle_c.ldp_extract_batch(buf, off, Hs, Ws, strides, k, 1, 1,
+                                                           magnitude=mag, threads=threads)
+            for j in range(len(Hs)):
+                assert (codes[coff[j]:coff[j + 1]] == want_c[j]).all(), (k, threads, j)
+                assert (hist[j] == want_h[j]).all(), (k, threads, j)
+    with pytest.raises(ValueError):       # a 2-row image anywhere in the batch
+        bad = Hs.copy()
+        bad[5] = 2
+        oracle_c.ldp_extract_batch(buf, off, bad, Ws, strides, 3, 1, 1)

@@ -1,6 +1,6 @@
 """Full-size workloads in the launch configuration the benchmark times:
-sampled images bit-exact against the oracle, every image checked by
-properties that hold at any size."""
+every image's codes and histograms bit-exact against the C oracle (run over
+the images on the host's cores), plus the properties that hold at any size."""
 import numpy as np
 import pytest
 
@@ -48,14 +48,16 @@ def _run(lib, name, k, n=None):
     return Hs, Ws, off, strides, host.numpy(), codes, coff, hist.view(len(Hs), cy, cx, 256), (cy, cx)
 
 
-def _check_sampled(Hs, Ws, off, strides, host, codes, coff, hist, cells, k, sample):
-    for j in sample:
-        H, W, s, o = int(Hs[j]), int(Ws[j]), int(strides[j]), int(off[j])
-        im = host[o:o + H * s].reshape(H, s)[:, :W]
-        wc, wh = oracle_c.ldp_extract(im, k, *cells)
-        gc = codes[int(coff[j]):int(coff[j + 1])].cpu().numpy().reshape(wc.shape)
-        assert (gc == wc).all(), ("codes", j)
-        assert (hist[j].cpu().numpy().view(np.uint32) == wh).all(), ("hist", j)
+def _check_all(Hs, Ws, off, strides, host, codes, coff, hist, cells, k):
+    """Every image of the batch against the oracle, element by element."""
+    want_c, want_off, want_h = oracle_c.ldp_extract_batch(host, off, Hs, Ws, strides, k, *cells)
+    assert (want_off == coff).all()
+    got_c = codes[:int(coff[-1])].cpu().numpy()
+    bad = np.flatnonzero(got_c != want_c)
+    assert bad.size == 0, ("codes differ", int(np.searchsorted(coff, bad[0], side="right") - 1))
+    got_h = hist.cpu().numpy().view(np.uint32)
+    diff = np.flatnonzero((got_h != want_h).reshape(len(Hs), -1).any(axis=1))
+    assert diff.size == 0, ("histograms differ", diff[:8].tolist())
 
 
 def _check_mass(Hs, Ws, hist, k):
@@ -70,7 +72,7 @@ def test_batch_workload_full_size(lib):
     """4096 x 490x640, k=3, 7x6 cells."""
     r = _run(lib, "batch", 3)
     Hs, Ws, hist = r[0], r[1], r[7]
-    _check_sampled(*r, k=3, sample=[0, 1, 2047, 4095])
+    _check_all(*r, k=3)
     _check_mass(Hs, Ws, hist, 3)
 
 
@@ -78,17 +80,16 @@ def test_uneven_workload_full_size(lib):
     """10,000 images with sides uniform in [48, 1024], k=3, 7x6 cells."""
     r = _run(lib, "uneven", 3)
     Hs, Ws, hist = r[0], r[1], r[7]
-    big = int(np.argmax(Hs.astype(np.int64) * Ws))
-    small = int(np.argmin(Hs.astype(np.int64) * Ws))
-    _check_sampled(*r, k=3, sample=[0, 1, 4999, 9999, big, small])
+    _check_all(*r, k=3)
     _check_mass(Hs, Ws, hist, 3)
 
 
 @pytest.mark.parametrize("k", [2, 3, 4])
 def test_large_workload_subset(lib, k):
     """8192x8192 images of the bandwidth workload (flat patches), 16x16 cells:
-    the batch path on 4 of the 64 images, one checked against the oracle."""
+    the batch path on 4 of the 64 images, all four checked against the
+    oracle."""
     r = _run(lib, "large", k, n=4)
     Hs, Ws, hist = r[0], r[1], r[7]
-    _check_sampled(*r, k=k, sample=[3])
+    _check_all(*r, k=k)
     _check_mass(Hs, Ws, hist, k)
