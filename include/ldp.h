@@ -374,6 +374,18 @@ int ldp_server_stats_get(ldp_server *server, ldp_server_stats *stats);
 /* Stop the dispatcher after the queued requests complete, release all. */
 int ldp_server_destroy(ldp_server *server);
 
+/* ---------------------------------------------------------------- measurement
+ *
+ * ldp_stream_copy -- copies `bytes` bytes from src to dst (device memory,
+ * both 16-byte aligned, not overlapping) with a plain streaming kernel that
+ * reads and writes every byte once.  Not part of the method: it is the
+ * measuring stick for the LDP kernels (the device-memory rate a kernel that
+ * touches each byte once reaches, and a kernel of known traffic for scaling
+ * hardware byte counters).  Errors: LDP_ERR_INVALID_ARG for bytes < 0, a null
+ * or misaligned pointer with bytes > 0; LDP_ERR_HIP for a failed launch.
+ */
+int ldp_stream_copy(const void *src, void *dst, int64_t bytes, ldp_stream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

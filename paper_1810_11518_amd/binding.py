@@ -34,7 +34,7 @@ EXPORTED = [
     "ldp_batch_plan_set", "ldp_batch_run", "ldp_batch_launch", "ldp_batch_run_per_image",
     "ldp_batch_plan_info", "ldp_batch_plan_destroy",
     "ldp_now", "ldp_server_create", "ldp_server_submit", "ldp_server_poll",
-    "ldp_server_stats_get", "ldp_server_destroy",
+    "ldp_server_stats_get", "ldp_server_destroy", "ldp_stream_copy",
 ]
 
 
@@ -154,6 +154,7 @@ def load():
                                            ctypes.POINTER(i32), i32]),
         "ldp_server_stats_get": (ctypes.c_int, [p, ctypes.POINTER(ServerStats)]),
         "ldp_server_destroy": (ctypes.c_int, [p]),
+        "ldp_stream_copy": (ctypes.c_int, [p, p, i64, p]),
     }
     for name, (res, args) in sig.items():
         if not hasattr(lib, name):
@@ -298,6 +299,17 @@ def compact_histograms(hist, k, out=None, stream=None):
     _check(load().ldp_compact_histograms(hist.data_ptr(), n_cells, k, out.data_ptr(),
                                          _stream(stream)), "ldp_compact_histograms")
     return out
+
+
+def stream_copy(src, dst, stream=None):
+    """Copy device tensor ``src`` into ``dst`` (same byte size, 16-byte
+    aligned) with the library's streaming copy kernel (ldp_stream_copy)."""
+    nb = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nb:
+        raise ValueError("src and dst differ in size")
+    _check(load().ldp_stream_copy(src.data_ptr(), dst.data_ptr(), nb, _stream(stream)),
+           "ldp_stream_copy")
+    return dst
 
 
 class BatchPlan:

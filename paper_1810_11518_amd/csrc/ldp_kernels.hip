@@ -1,7 +1,8 @@
 // ldp_kernels.hip -- single-image LDP kernels and their C ABI entry points.
 //
 //   ldp_codes       codes of every interior pixel (Eqs. 1-3)
-//   ldp_histograms  per-cell 256-bin histograms of a code map (Eqs. 4-5)
+//   ldp_histograms  per-cell 256-bin histograms of a code map (Eqs. 4-5;
+//                   the kernel is in ldp_hist.hip)
 //   ldp_extract     both in one launch, without reading the codes back
 #include "ldp_engine.hpp"
 #include "ldp_host.hpp"
@@ -40,41 +41,6 @@ __global__ void __launch_bounds__(256) LDP_CODES_ATTR codes_kernel(const uint8_t
         run_task_narrow<K, MODE, false, true>(im, nullptr, 0, none, r0, r1);
     else
         run_task<K, MODE, false, true>(im, nullptr, 0, group_cols<false>(im, none, g), r0, r1);
-}
-
-// ---------------------------------------------------------------- histograms
-// Block (cx, cy, split) counts the codes of cell (cy, cx), rows split in
-// `nsplit` parts.  Wave-private LDS bins; one store (or atomic add when the
-// cell is split) per bin.
-__global__ void __launch_bounds__(256) hist_kernel(const uint8_t *__restrict__ codes, int32_t Hc,
-                                                   int32_t Wc, Geom geo,
-                                                   uint32_t *__restrict__ hist, int32_t nsplit)
-{
-    __shared__ uint32_t bins[4][256];
-    const int tid = threadIdx.x, wave = tid >> 6;
-#pragma unroll
-    for (int w = 0; w < 4; ++w)
-        bins[w][tid] = 0;
-    __syncthreads();
-    const int32_t cx = blockIdx.x, cy = blockIdx.y, sp = blockIdx.z;
-    const int32_t ry0 = geom_row_start(geo, cy, Hc), ry1 = geom_row_start(geo, cy + 1, Hc);
-    const int32_t c0 = geom_col_start(geo, cx, Wc), c1 = geom_col_start(geo, cx + 1, Wc);
-    const int32_t nrows = ry1 - ry0, width = c1 - c0;
-    const int32_t a0 = ry0 + (int32_t)((int64_t)nrows * sp / nsplit);
-    const int32_t a1 = ry0 + (int32_t)((int64_t)nrows * (sp + 1) / nsplit);
-    const int64_t n = (int64_t)(a1 - a0) * width;
-    for (int64_t idx = tid; idx < n; idx += 256) {
-        int32_t r = a0 + (int32_t)(idx / width);
-        int32_t c = c0 + (int32_t)(idx % width);
-        atomicAdd(&bins[wave][codes[(int64_t)r * Wc + c]], 1u);
-    }
-    __syncthreads();
-    uint32_t total = bins[0][tid] + bins[1][tid] + bins[2][tid] + bins[3][tid];
-    uint32_t *dst = hist + ((int64_t)cy * geo.nx + cx) * 256 + tid;
-    if (nsplit == 1)
-        *dst = total;
-    else if (total)
-        atomicAdd(dst, total);
 }
 
 __global__ void zero_kernel(uint32_t *__restrict__ p, int64_t n)
@@ -166,28 +132,6 @@ int launch_codes(const uint8_t *img, int32_t H, int32_t W, int64_t stride, int32
     hipError_t e = dispatch<CodesLaunch>(k, rank_mode(flags), false, grid, block, s, img,
                                          stride, H, W, codes, band, ngroups, ntasks);
     return e == hipSuccess ? LDP_OK : LDP_ERR_HIP;
-}
-
-int launch_histograms(const uint8_t *codes, int32_t H, int32_t W, int32_t gy, int32_t gx,
-                      bool windows, uint32_t *hist, hipStream_t s)
-{
-    const int32_t Hc = H - 2, Wc = W - 2;
-    const Geom geo = make_geom(Hc, Wc, gy, gx, windows);
-    const int64_t cells = (int64_t)geo.ny * geo.nx;
-    const int64_t per_cell = (int64_t)Hc * Wc / cells;
-    // split cells so that there are enough workgroups and none is huge
-    int32_t nsplit = 1;
-    while (nsplit < 64 && (cells * nsplit < 512 || per_cell / nsplit > (1 << 16)) &&
-           (Hc / geo.ny) / (nsplit * 2) >= 1)
-        nsplit *= 2;
-    if (nsplit > 1) {
-        int64_t n = cells * 256;
-        hipLaunchKernelGGL(zero_kernel, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 1024)),
-                           dim3(256), 0, s, hist, n);
-    }
-    hipLaunchKernelGGL(hist_kernel, dim3(geo.nx, geo.ny, nsplit), dim3(256), 0, s, codes, Hc, Wc,
-                       geo, hist, nsplit);
-    return hipGetLastError() == hipSuccess ? LDP_OK : LDP_ERR_HIP;
 }
 
 // LDS bytes of one cell row of histograms plus its discard cell

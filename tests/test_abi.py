@@ -92,6 +92,11 @@ def test_invalid_arguments_return_before_any_launch(lib):
     assert lib.ldp_batch_plan_create_windows(ctypes.byref(plan), 10, 100, 2, 3, 0, 5, 5, None) == E
     assert (lib.ldp_batch_plan_create_windows(ctypes.byref(plan), 10, 10 ** 6, 1000, 3, 0, 5, 5,
                                               None) == binding.LDP_ERR_UNSUPPORTED)  # 200 windows
+    assert lib.ldp_stream_copy(p, p, -1, None) == E
+    assert lib.ldp_stream_copy(None, p, 16, None) == E
+    assert lib.ldp_stream_copy(p, None, 16, None) == E
+    assert lib.ldp_stream_copy(ctypes.c_void_p(0x1004), p, 16, None) == E   # not 16-byte aligned
+    assert lib.ldp_stream_copy(None, None, 0, None) == binding.LDP_OK      # nothing to do
     srv = ctypes.c_void_p()
     bad = binding.ServerConfig(0, 1, 1, 1, 3, 7, 6, 1, 0)
     assert lib.ldp_server_create(ctypes.byref(srv), ctypes.byref(bad)) == E

@@ -99,6 +99,36 @@ def test_histograms_match_oracle(lib, cells):
         assert (got == oracle_c.ldp_histograms(codes, cy, cx)).all(), (H, W, cells)
 
 
+@pytest.mark.parametrize("shift", [0, 1, 3])
+def test_histograms_kernel_layouts(lib, shift):
+    """The histogram kernel's layouts: code maps narrower than one 16-column
+    chunk, widths with and without 4-aligned rows, a code map starting at any
+    byte, cells narrower than 16 columns, more than 63 cells in a row (several
+    items per cell row), tall maps whose cell rows are split over workgroups
+    (atomic flush), and flat regions (one add of 16)."""
+    r = np.random.default_rng(40 + shift)
+    cases = [(5, 9, (1, 1)), (9, 14, (2, 3)), (20, 18, (3, 2)), (34, 66, (4, 4)),
+             (70, 130, (5, 9)), (300, 260, (16, 16)), (40, 1002, (2, 100)),
+             (1500, 42, (3, 1)), (2000, 2000, (1, 1)), (515, 1030, (7, 64))]
+    for H, W, (cy, cx) in cases:
+        img = synth.image(synth.KIND_BLUR_RECTS, 5, H * 7 + W, H, W)
+        codes = oracle_c.ldp_codes(img, int(r.integers(1, 9)))
+        if H * W % 3 == 0:
+            codes[: codes.shape[0] // 2] = 255          # a flat half: equal codes
+        n = codes.size
+        buf = torch.zeros(shift + n + 16, dtype=torch.uint8, device="cuda")
+        buf[shift:shift + n] = torch.from_numpy(codes.ravel()).cuda()
+        dev = buf[shift:shift + n].view(codes.shape)
+        got = lib.histograms(dev, cy, cx).cpu().numpy().view(np.uint32)
+        assert (got == oracle_c.ldp_histograms(codes, cy, cx)).all(), (H, W, cy, cx, shift)
+        for w in (3, 16, 25):
+            if (codes.shape[0] // w + 1) * (codes.shape[1] // w + 1) > 20000:
+                continue                                  # the oracle loops over windows
+            got = lib.histograms_windows(dev, w, w).cpu().numpy().view(np.uint32)
+            want = oracle_np.window_histograms(codes, w, w)
+            assert (got == want).all(), (H, W, w, shift)
+
+
 def test_histograms_one_pixel_cells(lib):
     img = np.random.default_rng(4).integers(0, 256, (12, 14), dtype=np.uint8)
     codes = oracle_c.ldp_codes(img, 3)
