@@ -176,9 +176,8 @@ int ldp_window_grid(int32_t H, int32_t W, int32_t win_y, int32_t win_x, int32_t 
 int ldp_histograms_windows(const uint8_t *codes, int32_t H, int32_t W, int32_t win_y,
                            int32_t win_x, uint32_t *hist, ldp_stream_t stream);
 
-/* ldp_extract_windows -- ldp_extract_ex with windows.  With nx > 63 the
- * histograms are counted in a second pass over the code map, so `codes` must
- * not be NULL then (LDP_ERR_UNSUPPORTED). */
+/* ldp_extract_windows -- ldp_extract_ex with windows (one launch; `codes` may
+ * be NULL for any window grid). */
 int ldp_extract_windows(const uint8_t *img, int32_t H, int32_t W, int64_t stride, int32_t k,
                         int32_t flags, int32_t win_y, int32_t win_x, uint8_t *codes,
                         uint32_t *hist, ldp_stream_t stream);
@@ -208,8 +207,10 @@ typedef struct ldp_image_desc {
 typedef struct ldp_size_class {
     int64_t max_pixels;         /* upper bound of H*W for the class */
     int32_t cell_rows_per_item; /* cell rows of one image per work item, >= 1; lowered so
-                                   that an item's histograms ((cells_x + 1) KiB per cell row,
-                                   in LDS) take at most 32 KiB, or one cell row */
+                                   that an item's histograms ((c + 1) KiB per cell row in LDS,
+                                   c = the cells of a row one item covers: all of them, or a
+                                   run of at most 63 when a row has more) take at most 32 KiB,
+                                   or one cell row */
     int32_t rows_per_task;      /* target code rows per lane task, >= 1 */
 } ldp_size_class;
 
@@ -240,9 +241,9 @@ int ldp_batch_plan_create_ex(ldp_batch_plan **plan, int32_t max_images, int64_t 
 
 /* A plan whose runs give each image ldp_extract_windows' results (every
  * image's hist holds its own ny*nx*256 bins).  Images may be at most
- * max_width columns wide (wider ones: LDP_ERR_INVALID_ARG from set);
- * ceil((max_width-2)/win_x) must be <= 63, else LDP_ERR_UNSUPPORTED.  The
- * plan's device work table grows when a batch needs more work items. */
+ * max_width columns wide (wider ones: LDP_ERR_INVALID_ARG from set).  A row
+ * of more than 63 windows is split over several work items.  The plan's
+ * device work table grows when a batch needs more work items. */
 int ldp_batch_plan_create_windows(ldp_batch_plan **plan, int32_t max_images, int64_t max_pixels,
                                   int32_t max_width, int32_t k, int32_t flags, int32_t win_y,
                                   int32_t win_x, const ldp_tune *tune);

@@ -22,10 +22,20 @@
 
 namespace ldp {
 
+// A work item: cell rows [cy0, cy1) and cell columns [cx0, cx1) of one image
+// (at most 65534 of either).  The image's size class (whose target code rows
+// per lane task the kernel takes from its MinRows argument) sits in the top
+// two bits of `img`, the descriptor index in the rest.
 struct Item {
-    int32_t img;        // index into the descriptor table
-    uint16_t cy0, cy1;  // cell rows [cy0, cy1) (at most 65534 cell rows)
-    int32_t min_rows;   // target code rows per lane task
+    uint32_t img;
+    uint16_t cy0, cy1;
+    uint16_t cx0, cx1;
+};
+constexpr uint32_t kImgBits = 30;
+constexpr int32_t kMaxPlanImages = (int32_t)(1u << kImgBits);
+
+struct MinRows {
+    int32_t v[LDP_MAX_SIZE_CLASSES];
 };
 
 // The queue of a launch: item count, next item number, workgroups that found
@@ -67,7 +77,8 @@ struct DeviceTables {
         w.img = ci.img;
         w.cy0 = ci.cy0;
         w.cy1 = ci.cy1;
-        w.min_rows = ci.min_rows;
+        w.cx0 = ci.cx0;
+        w.cx1 = ci.cx1;
         return w;
     }
     __device__ __forceinline__ ldp_image_desc desc(int32_t j) const { return descs[j]; }
@@ -98,7 +109,7 @@ struct ArgTables {
 template <int K, int MODE, class Tables>
 __device__ __forceinline__ void run_queue(const Tables &tab, uint32_t n_items, Meta *meta,
                                           int32_t gy, int32_t gx, int32_t windows,
-                                          int32_t item_slot)
+                                          int32_t item_slot, const MinRows &min_rows)
 {
     extern __shared__ uint32_t lds[];
     uint32_t &s_item = lds[item_slot];
@@ -111,14 +122,16 @@ __device__ __forceinline__ void run_queue(const Tables &tab, uint32_t n_items, M
         if (it >= n_items)
             break;
         const Item w = tab.item(it);
-        const ldp_image_desc d = tab.desc(w.img);
+        const ldp_image_desc d = tab.desc((int32_t)(w.img & ((1u << kImgBits) - 1u)));
+        const int32_t task_rows = min_rows.v[w.img >> kImgBits];
         uint32_t *hist = d.hist;
         ImgView im = make_view(d.img, d.stride, d.H, d.W, d.codes);
         const Geom geo = make_geom(im.Hc, im.Wc, gy, gx, windows != 0);
         const int32_t r0 = geom_row_start(geo, w.cy0, im.Hc);
         const int32_t r1 = geom_row_start(geo, w.cy1, im.Hc);
         // a null code pointer gives an empty store range: stores are dropped
-        fused_item<K, MODE, true>(im, lds, geo, w.cy0, w.cy1, r0, r1, hist, false, w.min_rows);
+        fused_item<K, MODE, true>(im, lds, geo, w.cy0, w.cy1, w.cx0, w.cx1, r0, r1, hist, false,
+                                  task_rows);
     }
     // Every workgroup has taken its last number once all have counted
     // themselves here: the last one resets the queue for the next launch
@@ -132,7 +145,8 @@ __device__ __forceinline__ void run_queue(const Tables &tab, uint32_t n_items, M
 template <int K, int MODE>
 __global__ void __launch_bounds__(1024) LDP_BATCH_ATTR batch_kernel(const ldp_image_desc *__restrict__ descs,
                                                      Meta *meta, int32_t gy, int32_t gx,
-                                                     int32_t windows, int32_t item_slot)
+                                                     int32_t windows, int32_t item_slot,
+                                                     MinRows min_rows)
 {
     // the item count and table address are the same for every lane:
     // readfirstlane keeps them (and what is read through them) in scalar
@@ -140,7 +154,7 @@ __global__ void __launch_bounds__(1024) LDP_BATCH_ATTR batch_kernel(const ldp_im
     const uint32_t n_items = uniform(meta->n_items);
     const DeviceTables tab{
         (const ConstItem *)(uintptr_t)uniform64(reinterpret_cast<uint64_t>(meta->items)), descs};
-    run_queue<K, MODE>(tab, n_items, meta, gy, gx, windows, item_slot);
+    run_queue<K, MODE>(tab, n_items, meta, gy, gx, windows, item_slot, min_rows);
 }
 
 // The same pass over a batch given in the arguments; only the queue counter
@@ -148,12 +162,13 @@ __global__ void __launch_bounds__(1024) LDP_BATCH_ATTR batch_kernel(const ldp_im
 template <int K, int MODE>
 __global__ void __launch_bounds__(1024) LDP_BATCH_ATTR batch_arg_kernel(const ArgBatch b, Meta *meta,
                                                          int32_t gy, int32_t gx,
-                                                         int32_t windows, int32_t item_slot)
+                                                         int32_t windows, int32_t item_slot,
+                                                         MinRows min_rows)
 {
-    run_queue<K, MODE>(ArgTables{&b}, b.n_items, meta, gy, gx, windows, item_slot);
+    run_queue<K, MODE>(ArgTables{&b}, b.n_items, meta, gy, gx, windows, item_slot, min_rows);
 }
 
-typedef void (*batch_arg_fn)(const ArgBatch, Meta *, int32_t, int32_t, int32_t, int32_t);
+typedef void (*batch_arg_fn)(const ArgBatch, Meta *, int32_t, int32_t, int32_t, int32_t, MinRows);
 
 static batch_arg_fn batch_arg_kernel_for(int k)
 {
@@ -170,7 +185,8 @@ static batch_arg_fn batch_arg_kernel_for(int k)
     return nullptr;
 }
 
-typedef void (*batch_fn)(const ldp_image_desc *, Meta *, int32_t, int32_t, int32_t, int32_t);
+typedef void (*batch_fn)(const ldp_image_desc *, Meta *, int32_t, int32_t, int32_t, int32_t,
+                         MinRows);
 
 template <int MODE>
 static batch_fn batch_kernel_for_mode(int k)
@@ -203,12 +219,14 @@ static batch_fn batch_kernel_for(int k, int mode)
 struct ldp_batch_plan {
     int32_t k = 3, flags = 0, max_images = 0;
     int32_t gy = 1, gx = 1;  // cells_y, cells_x, or window sides when `windows`
+    int32_t max_width = LDP_MAX_SIDE;  // widest image a window plan takes
     bool windows = false;
-    int32_t nx_max = 1;      // most cell columns of an image (LDS sizing)
+    int32_t nx_max = 1;      // most cells of a cell row in one work item (LDS sizing), <= 63
     int64_t max_pixels = 0, max_items = 0;
     int32_t threads = 256, grid = 0;
     int32_t n_classes = 1;
     ldp_size_class classes[LDP_MAX_SIZE_CLASSES] = {{INT64_MAX, 1, 8}};
+    ldp::MinRows min_rows{};   // classes[c].rows_per_task, as the kernels take them
     size_t lds_bytes = 0;
     int device = 0;
     // One device block and its pinned staging mirror, laid out as
@@ -257,11 +275,16 @@ void release(ldp_batch_plan *p)
 namespace {
 
 // Shared by the cell-grid and window plans; nx_max bounds an image's cell
-// columns (the LDS of an item holds its cell rows of nx_max + 1 cells).
+// columns.  Cell rows wider than 63 cells are cut into runs of near-equal
+// length (cell_runs); the plan keeps that run length as nx_max, cuts every
+// image's cell rows into runs no longer than it, and sizes an item's LDS for
+// nx_max + 1 cells per cell row.
 int create_plan(ldp_batch_plan **out, int32_t max_images, int64_t max_pixels, int32_t k,
                 int32_t flags, bool windows, int32_t gy, int32_t gx, int32_t nx_max,
                 const ldp_tune *tune)
 {
+    const int32_t runs_max = ldp::cell_runs(nx_max);
+    nx_max = (nx_max + runs_max - 1) / runs_max;
     *out = nullptr;
     ldp_batch_plan *p = new (std::nothrow) ldp_batch_plan();
     if (!p)
@@ -320,9 +343,12 @@ int create_plan(ldp_batch_plan **out, int32_t max_images, int64_t max_pixels, in
         min_cpi = std::min(min_cpi, sc.cell_rows_per_item);
     }
     p->classes[p->n_classes - 1].max_pixels = INT64_MAX;
+    for (int c = 0; c < LDP_MAX_SIZE_CLASSES; ++c)
+        p->min_rows.v[c] = p->classes[std::min(c, p->n_classes - 1)].rows_per_task;
     // item table: enough for max_images images of a cell grid; window plans
     // start at 8 items per image and grow when a batch needs more
-    p->max_items = (int64_t)max_images * (windows ? 8 : (gy + min_cpi - 1) / min_cpi);
+    p->max_items = (int64_t)max_images *
+                   (windows ? 8 : (int64_t)((gy + min_cpi - 1) / min_cpi) * runs_max);
     // LDS: the largest item's cell rows, each with its discard cell, then the
     // item broadcast word (16 bytes keep the allocation aligned)
     const size_t hist_bytes = (size_t)max_cpi * ldp::hist_row_bytes(nx_max);
@@ -370,7 +396,7 @@ int create_plan(ldp_batch_plan **out, int32_t max_images, int64_t max_pixels, in
         return fail(LDP_ERR_HIP);
     hipLaunchKernelGGL(fn, dim3(p->grid), dim3(p->threads), p->lds_bytes, p->cap_stream,
                        (const ldp_image_desc *)p->d_descs, p->d_meta, gy, gx, windows ? 1 : 0,
-                       (int32_t)(hist_bytes / 4));
+                       (int32_t)(hist_bytes / 4), p->min_rows);
     hipError_t ce = hipStreamEndCapture(p->cap_stream, &p->graph);
     if (ce != hipSuccess || hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) !=
                                 hipSuccess)
@@ -382,7 +408,8 @@ int create_plan(ldp_batch_plan **out, int32_t max_images, int64_t max_pixels, in
 bool common_args_ok(ldp_batch_plan **out, int32_t max_images, int64_t max_pixels, int32_t k,
                     int32_t flags)
 {
-    return out && max_images >= 1 && max_pixels >= 9 && k >= 1 && k <= 8 && ldp::flags_ok(flags);
+    return out && max_images >= 1 && max_images < ldp::kMaxPlanImages && max_pixels >= 9 &&
+           k >= 1 && k <= 8 && ldp::flags_ok(flags);
 }
 
 }  // namespace
@@ -406,7 +433,7 @@ int cut_items(const ldp_batch_plan *p, const ldp_image_desc *descs, int32_t n,
             return LDP_ERR_INVALID_ARG;
         if (!p->windows && (d.H - 2 < p->gy || d.W - 2 < p->gx))
             return LDP_ERR_INVALID_ARG;
-        if (p->windows && ldp::make_geom(d.H - 2, d.W - 2, p->gy, p->gx, true).nx > p->nx_max)
+        if (p->windows && d.W > p->max_width)
             return LDP_ERR_INVALID_ARG;  // wider than the plan's max_width
         pixels += (int64_t)d.H * d.W;
     }
@@ -420,14 +447,22 @@ int cut_items(const ldp_batch_plan *p, const ldp_image_desc *descs, int32_t n,
         while (c < p->n_classes - 1 && px > p->classes[c].max_pixels)
             ++c;
         const int32_t cpi = p->classes[c].cell_rows_per_item;
-        const int32_t Hc = descs[j].H - 2;
-        const ldp::Geom geo = ldp::make_geom(Hc, descs[j].W - 2, p->gy, p->gx, p->windows);
+        const int32_t Hc = descs[j].H - 2, Wc = descs[j].W - 2;
+        const ldp::Geom geo = ldp::make_geom(Hc, Wc, p->gy, p->gx, p->windows);
+        // runs of at most the plan's nx_max cells (the LDS of an item)
+        const int32_t runs = (geo.nx + p->nx_max - 1) / p->nx_max;
         for (int32_t cy = 0; cy < geo.ny; cy += cpi) {
             const int32_t cy1 = std::min(cy + cpi, geo.ny);
-            items.push_back({j, (uint16_t)cy, (uint16_t)cy1, p->classes[c].rows_per_task});
             const int64_t rows =
                 ldp::geom_row_start(geo, cy1, Hc) - ldp::geom_row_start(geo, cy, Hc);
-            size.push_back(rows * (descs[j].W - 2));
+            for (int32_t xi = 0; xi < runs; ++xi) {
+                const int32_t cx0 = ldp::cell_run_start(geo.nx, runs, xi);
+                const int32_t cx1 = ldp::cell_run_start(geo.nx, runs, xi + 1);
+                items.push_back({(uint32_t)j | ((uint32_t)c << ldp::kImgBits), (uint16_t)cy,
+                                 (uint16_t)cy1, (uint16_t)cx0, (uint16_t)cx1});
+                size.push_back(rows * (ldp::geom_col_start(geo, cx1, Wc) -
+                                       ldp::geom_col_start(geo, cx0, Wc)));
+            }
         }
     }
     if ((int64_t)items.size() > p->max_items && !p->windows)
@@ -451,7 +486,7 @@ int ldp_batch_plan_create_ex(ldp_batch_plan **out, int32_t max_images, int64_t m
                              const ldp_tune *tune)
 {
     if (!common_args_ok(out, max_images, max_pixels, k, flags) || cells_y < 1 || cells_x < 1 ||
-        cells_y > LDP_MAX_SIDE - 2 || cells_x > ldp::kMaxFusedCellsX)
+        cells_y > LDP_MAX_SIDE - 2 || cells_x > LDP_MAX_SIDE - 2)
         return LDP_ERR_INVALID_ARG;
     return create_plan(out, max_images, max_pixels, k, flags, false, cells_y, cells_x, cells_x,
                        tune);
@@ -466,9 +501,13 @@ int ldp_batch_plan_create_windows(ldp_batch_plan **out, int32_t max_images, int6
         return LDP_ERR_INVALID_ARG;
     const int32_t wc = max_width - 2, wx = std::min(win_x, wc);
     const int32_t nx_max = (wc + wx - 1) / wx;
-    if (nx_max > ldp::kMaxFusedCellsX)
-        return LDP_ERR_UNSUPPORTED;
-    return create_plan(out, max_images, max_pixels, k, flags, true, win_y, win_x, nx_max, tune);
+    ldp_batch_plan *p = nullptr;
+    const int st = create_plan(&p, max_images, max_pixels, k, flags, true, win_y, win_x, nx_max,
+                               tune);
+    if (st == LDP_OK)
+        p->max_width = max_width;
+    *out = p;
+    return st;
 }
 
 int ldp_batch_plan_create(ldp_batch_plan **out, int32_t max_images, int64_t max_pixels, int32_t k,
@@ -607,7 +646,8 @@ int launch_args(const ldp_batch_plan *p, batch_arg_fn fn, ArgBatch &b, hipStream
     Meta *meta = p->d_meta;
     int32_t gy = p->gy, gx = p->gx, windows = 0;
     int32_t item_slot = (int32_t)((p->lds_bytes - 16) / 4);
-    void *args[] = {&b, &meta, &gy, &gx, &windows, &item_slot};
+    MinRows min_rows = p->min_rows;
+    void *args[] = {&b, &meta, &gy, &gx, &windows, &item_slot, &min_rows};
     return hipLaunchKernel(reinterpret_cast<const void *>(fn), dim3(grid), dim3(p->threads), args,
                            p->lds_bytes, s) == hipSuccess
                ? LDP_OK

@@ -119,8 +119,18 @@ __host__ __device__ __forceinline__ int32_t geom_col_start(const Geom &g, int32_
     return j < Wc ? j : Wc;
 }
 
-// LDS histograms of a work item: per cell row, nx cells of 256 uint32 bins
-// followed by one discard cell (pixels that another lane counts).
+// Cell columns of a row cut into runs for workgroups whose LDS holds at
+// most 63 cells of a cell row: cell_runs(nx) runs of near-equal length (at
+// least 32 cells each when nx > 63), run i starting at cell_run_start.
+__host__ __device__ __forceinline__ int32_t cell_runs(int32_t nx) { return (nx + 62) / 63; }
+__host__ __device__ __forceinline__ int32_t cell_run_start(int32_t nx, int32_t runs, int32_t i)
+{
+    return (int32_t)((int64_t)nx * i / runs);
+}
+
+// LDS histograms of a work item: per cell row, its nx cells (of the item's
+// column range) of 256 uint32 bins followed by one discard cell (pixels that
+// another lane or item counts).
 __host__ __device__ __forceinline__ uint32_t hist_row_bytes(int32_t nx)
 {
     return (uint32_t)(nx + 1) * 1024u;
@@ -163,11 +173,13 @@ __device__ __forceinline__ void unpack_raw(Row &r, const RawRow &rr)
     }
 }
 
-// Column group of a lane: its first code column (groups of 8, the last one
-// ends at Wc - 1) and the histogram cell column of each pixel, one byte per
-// pixel, laid out like the code words of code_row (bytes of d0: pixels 0, 1,
-// 4, 5; of d1: pixels 2, 3, 6, 7); the discard cell (nx) for the leading
-// columns the previous group counts.
+// Column group of a lane inside the item's column range [c_lo, c_hi): its
+// first code column (groups of 8 from c_lo, the last one moved left to end at
+// c_hi - 1) and the LDS cell of each pixel, one byte per pixel, laid out like
+// the code words of code_row (bytes of d0: pixels 0, 1, 4, 5; of d1: pixels
+// 2, 3, 6, 7): the cell column minus cx0, or the discard cell (ncell) for the
+// leading columns that the previous group counts.  A range is at least 8
+// columns wide.
 struct Cols {
     int32_t j0;
     uint32_t d0, d1;
@@ -175,26 +187,27 @@ struct Cols {
 };
 
 template <bool HIST>
-__device__ __forceinline__ Cols group_cols(const ImgView &im, const Geom &geo, int32_t g)
+__device__ __forceinline__ Cols group_cols(const Geom &geo, int32_t g, int32_t c_lo, int32_t c_hi,
+                                           int32_t cx0, int32_t ncell, int32_t Wc)
 {
     Cols c;
-    c.j0 = min(8 * g, im.Wc - 8);
+    c.j0 = min(c_lo + 8 * g, c_hi - 8);
     c.d0 = c.d1 = 0;
     c.uniform_cell = false;
     if constexpr (HIST) {
-        const int32_t skip = 8 * g - c.j0;
+        const int32_t skip = c_lo + 8 * g - c.j0;
         // Cells at least 8 columns wide (the usual case, decided per image):
         // the 8 columns meet at most one cell boundary, so two divisions (the
         // first column's cell and the next cell's first column) place them
         // all.  Narrower cells: one division per column.
         const bool wide = geo.bx >= 8u * geo.ax;
-        const uint32_t cx0 = ((uint32_t)c.j0 * geo.ax) / geo.bx;
-        const uint32_t next = wide ? (uint32_t)geom_col_start(geo, (int32_t)cx0 + 1, im.Wc) : 0u;
+        const uint32_t cxa = ((uint32_t)c.j0 * geo.ax) / geo.bx;
+        const uint32_t next = wide ? (uint32_t)geom_col_start(geo, (int32_t)cxa + 1, Wc) : 0u;
 #pragma unroll
         for (int p = 0; p < 8; ++p) {
             const uint32_t j = (uint32_t)(c.j0 + p);
-            const uint32_t cx = wide ? cx0 + (j >= next ? 1u : 0u) : (j * geo.ax) / geo.bx;
-            const uint32_t d = (p < skip ? (uint32_t)geo.nx : cx)
+            const uint32_t cx = wide ? cxa + (j >= next ? 1u : 0u) : (j * geo.ax) / geo.bx;
+            const uint32_t d = (p < skip ? (uint32_t)ncell : cx - (uint32_t)cx0)
                                << (8 * ((p & 1) | ((p >> 1) & 2)));
             if (p & 2)
                 c.d1 |= d;
@@ -383,9 +396,14 @@ __device__ void run_task_narrow(const ImgView &im, uint32_t *lds_bins, uint32_t 
 }
 
 // ---------------------------------------------------------------- work items
-// One workgroup per work item: code rows [r0, r1) of cell rows [cy0, cy1).
-// When r0/r1 cut a cell row (an image split across workgroups) the flush adds
-// atomically into a zeroed histogram; otherwise it stores.
+// One workgroup per work item: code rows [r0, r1) of cell rows [cy0, cy1) and
+// the cells [cx0, cx1) of those rows (all of them, or a run of at most 63
+// when a cell row has more cells than one workgroup's LDS holds; the ranges
+// of an image's items tile its cell columns).  When r0/r1 cut a cell row (an
+// image split across workgroups) the flush adds atomically into a zeroed
+// histogram; otherwise it stores.  Columns just outside the range that a
+// group shifted to the range's end computes are stored again with the same
+// codes and counted in the discard cell.
 //
 // Work split: a task is (row band, column group) of one cell row, and a lane
 // keeps the same task in every cell row of the item.  With q = threads /
@@ -397,13 +415,15 @@ __device__ void run_task_narrow(const ImgView &im, uint32_t *lds_bins, uint32_t 
 // Wider maps (more column groups than threads) take whole cell rows per task.
 template <int K, int MODE, bool CODES>
 __device__ __forceinline__ void fused_item(const ImgView &im, uint32_t *lds, const Geom &geo,
-                                           int32_t cy0, int32_t cy1, int32_t r0,
-                                           int32_t r1, uint32_t *hist, bool atomic_flush,
-                                           int32_t min_task_rows)
+                                           int32_t cy0, int32_t cy1, int32_t cx0, int32_t cx1,
+                                           int32_t r0, int32_t r1, uint32_t *hist,
+                                           bool atomic_flush, int32_t min_task_rows)
 {
     const int tid = threadIdx.x, nthreads = blockDim.x;
-    const uint32_t row_bytes = hist_row_bytes(geo.nx);
-    const int32_t row_words = (geo.nx + 1) * 256;
+    const int32_t ncell = cx1 - cx0;
+    const uint32_t row_bytes = hist_row_bytes(ncell);
+    const int32_t row_words = (ncell + 1) * 256;
+    const int32_t c_lo = geom_col_start(geo, cx0, im.Wc), c_hi = geom_col_start(geo, cx1, im.Wc);
     // 16-byte LDS writes (the histograms start 16-byte aligned and every
     // cell row is a multiple of 1 KB)
     uint4 *lds4 = reinterpret_cast<uint4 *>(lds);
@@ -429,7 +449,7 @@ __device__ __forceinline__ void fused_item(const ImgView &im, uint32_t *lds, con
             }
         }
     } else {
-        const int32_t ngroups = (im.Wc + 7) / 8;
+        const int32_t ngroups = (c_hi - c_lo + 7) / 8;
         // operands below 2^16 (threads <= 1024, rows <= 65534): udiv_small
         const int32_t q = (int32_t)udiv_small((uint32_t)nthreads, (uint32_t)ngroups);
         if (q >= 1) {
@@ -451,7 +471,7 @@ __device__ __forceinline__ void fused_item(const ImgView &im, uint32_t *lds, con
                     g = (uint32_t)(ngroups - nx) + (uint32_t)(tid - base) - sb * (uint32_t)nx;
                     nb = (uint32_t)nsub + 1;
                 }
-                const Cols c = group_cols<true>(im, geo, (int32_t)g);
+                const Cols c = group_cols<true>(geo, (int32_t)g, c_lo, c_hi, cx0, ncell, im.Wc);
                 for (int32_t cy = cy0; cy < cy1; ++cy) {
                     if (cy > cy0) {
                         a = b;
@@ -475,8 +495,9 @@ __device__ __forceinline__ void fused_item(const ImgView &im, uint32_t *lds, con
                     b = min(r1, geom_row_start(geo, cy + 1, im.Hc));
                 }
                 for (int32_t g = tid; g < ngroups; g += nthreads)
-                    run_task<K, MODE, true, CODES>(im, lds, (cy - cy0) * row_bytes,
-                                             group_cols<true>(im, geo, g), a, b);
+                    run_task<K, MODE, true, CODES>(
+                        im, lds, (cy - cy0) * row_bytes,
+                        group_cols<true>(geo, g, c_lo, c_hi, cx0, ncell, im.Wc), a, b);
             }
         }
     }
@@ -489,16 +510,17 @@ __device__ __forceinline__ void fused_item(const ImgView &im, uint32_t *lds, con
         typedef __attribute__((address_space(1))) u32x4 global_u32x4;
         for (int32_t r = 0; r < cy1 - cy0; ++r) {
             const u32x4 *src = reinterpret_cast<const u32x4 *>(lds + r * row_words);
-            global_u32x4 *dst = (global_u32x4 *)(hist + (int64_t)(cy0 + r) * geo.nx * 256);
-            for (int32_t i = tid; i < geo.nx * 64; i += nthreads)
+            global_u32x4 *dst =
+                (global_u32x4 *)(hist + ((int64_t)(cy0 + r) * geo.nx + cx0) * 256);
+            for (int32_t i = tid; i < ncell * 64; i += nthreads)
                 dst[i] = src[i];
         }
         return;
     }
     for (int32_t r = 0; r < cy1 - cy0; ++r) {
         const uint32_t *src = lds + r * row_words;
-        global_u32 *dst = (global_u32 *)(hist + (int64_t)(cy0 + r) * geo.nx * 256);
-        for (int32_t i = tid; i < geo.nx * 256; i += nthreads) {
+        global_u32 *dst = (global_u32 *)(hist + ((int64_t)(cy0 + r) * geo.nx + cx0) * 256);
+        for (int32_t i = tid; i < ncell * 256; i += nthreads) {
             const uint32_t v = src[i];
             if (!atomic_flush)
                 dst[i] = v;

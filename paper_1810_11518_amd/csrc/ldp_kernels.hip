@@ -40,7 +40,8 @@ __global__ void __launch_bounds__(256) LDP_CODES_ATTR codes_kernel(const uint8_t
     if (im.Wc < 8)
         run_task_narrow<K, MODE, false, true>(im, nullptr, 0, none, r0, r1);
     else
-        run_task<K, MODE, false, true>(im, nullptr, 0, group_cols<false>(im, none, g), r0, r1);
+        run_task<K, MODE, false, true>(im, nullptr, 0,
+                                       group_cols<false>(none, g, 0, im.Wc, 0, 0, im.Wc), r0, r1);
 }
 
 __global__ void zero_kernel(uint32_t *__restrict__ p, int64_t n)
@@ -51,19 +52,22 @@ __global__ void zero_kernel(uint32_t *__restrict__ p, int64_t n)
 }
 
 // ---------------------------------------------------------------- fused
+// Workgroup = (cell row cy, cell-column run xi of nxi, row part sp of split).
 template <int K, int MODE, bool CODES>
 __global__ void __launch_bounds__(1024) fused_kernel(const uint8_t *__restrict__ img,
                                                      int64_t stride, int32_t H, int32_t W,
                                                      uint8_t *codes, uint32_t *hist, Geom geo,
-                                                     int32_t split)
+                                                     int32_t nxi, int32_t split)
 {
     extern __shared__ uint32_t lds[];
     const ImgView im = make_view(img, stride, H, W, codes);
-    const int32_t cy = blockIdx.x / split, sp = blockIdx.x % split;
+    const int32_t sp = blockIdx.x % split, t = blockIdx.x / split;
+    const int32_t xi = t % nxi, cy = t / nxi;
+    const int32_t cx0 = cell_run_start(geo.nx, nxi, xi), cx1 = cell_run_start(geo.nx, nxi, xi + 1);
     const int32_t ry0 = geom_row_start(geo, cy, im.Hc), ry1 = geom_row_start(geo, cy + 1, im.Hc);
     const int32_t r0 = ry0 + (int32_t)((int64_t)(ry1 - ry0) * sp / split);
     const int32_t r1 = ry0 + (int32_t)((int64_t)(ry1 - ry0) * (sp + 1) / split);
-    fused_item<K, MODE, CODES>(im, lds, geo, cy, cy + 1, r0, r1, hist, split > 1, 4);
+    fused_item<K, MODE, CODES>(im, lds, geo, cy, cy + 1, cx0, cx1, r0, r1, hist, split > 1, 4);
 }
 
 // ---------------------------------------------------------------- dispatch
@@ -110,10 +114,10 @@ template <int K, int MODE, bool CODES>
 struct FusedLaunch {
     static hipError_t launch(dim3 grid, dim3 block, size_t lds, hipStream_t s, const uint8_t *img,
                              int64_t stride, int32_t H, int32_t W, uint8_t *codes,
-                             uint32_t *hist, Geom geo, int32_t split)
+                             uint32_t *hist, Geom geo, int32_t nxi, int32_t split)
     {
         hipLaunchKernelGGL((fused_kernel<K, MODE, CODES>), grid, block, lds, s, img, stride, H, W,
-                           codes, hist, geo, split);
+                           codes, hist, geo, nxi, split);
         return hipGetLastError();
     }
 };
@@ -134,38 +138,33 @@ int launch_codes(const uint8_t *img, int32_t H, int32_t W, int64_t stride, int32
     return e == hipSuccess ? LDP_OK : LDP_ERR_HIP;
 }
 
-// LDS bytes of one cell row of histograms plus its discard cell
-static size_t fused_lds_bytes(int32_t nx) { return hist_row_bytes(nx); }
-
 int launch_extract(const uint8_t *img, int32_t H, int32_t W, int64_t stride, int32_t k,
                    int32_t flags, int32_t gy, int32_t gx, bool windows, uint8_t *codes,
                    uint32_t *hist, hipStream_t s)
 {
     const int32_t Hc = H - 2, Wc = W - 2;
     const Geom geo = make_geom(Hc, Wc, gy, gx, windows);
-    if (geo.nx > kMaxFusedCellsX) {
-        // one cell row of histograms does not fit in LDS: two passes
-        if (!codes)
-            return LDP_ERR_UNSUPPORTED;
-        int st = launch_codes(img, H, W, stride, k, flags, codes, s);
-        return st != LDP_OK ? st : launch_histograms(codes, H, W, gy, gx, windows, hist, s);
-    }
-    const int32_t ngroups = (Wc + 7) / 8;
+    // cell rows with more cells than one workgroup's LDS holds are cut into
+    // runs of at most kMaxFusedCellsX cells
+    const int32_t nxi = cell_runs(geo.nx);
+    const int32_t run_cells = (geo.nx + nxi - 1) / nxi;
+    const int32_t ngroups = (geom_col_start(geo, run_cells, Wc) + 7) / 8;
     int threads = ngroups >= 768 ? 1024 : ngroups >= 384 ? 512 : 256;
     // enough workgroups to fill the device: split cell rows
     int32_t split = 1;
     const int32_t rows_per_cell = Hc / geo.ny;
-    while ((int64_t)geo.ny * split < 512 && rows_per_cell / (split * 2) >= 8 && split < 64)
+    while ((int64_t)geo.ny * nxi * split < 512 && rows_per_cell / (split * 2) >= 8 && split < 64)
         split *= 2;
     if (split > 1) {
         int64_t n = (int64_t)geo.ny * geo.nx * 256;
         hipLaunchKernelGGL(zero_kernel, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 1024)),
                            dim3(256), 0, s, hist, n);
     }
-    size_t lds = fused_lds_bytes(geo.nx);
+    const size_t lds = hist_row_bytes(run_cells);
     hipError_t e = dispatch<FusedLaunch>(k, rank_mode(flags), codes != nullptr,
-                                         dim3(geo.ny * split), dim3(threads), lds, s, img,
-                                         stride, H, W, codes, hist, geo, split);
+                                         dim3((unsigned)((int64_t)geo.ny * nxi * split)),
+                                         dim3(threads), lds, s, img, stride, H, W, codes, hist,
+                                         geo, nxi, split);
     return e == hipSuccess ? LDP_OK : LDP_ERR_HIP;
 }
 

@@ -258,6 +258,11 @@ void dispatcher(ldp_server *s)
                 // device work without the lock: submit() keeps running
                 lk.unlock();
                 b.status = launch_batch(s, b);
+                if (b.status != LDP_OK && !s->cfg.dry_run &&
+                    hipEventRecord(s->events[slot], s->streams[slot]) != hipSuccess)
+                    // copies enqueued before the failure may still write into
+                    // this batch's pool regions: retire it only once they end
+                    (void)hipStreamSynchronize(s->streams[slot]);
                 b.t_launch = now_s();
                 lk.lock();
                 s->inflight.push_back(std::move(b));
@@ -312,7 +317,7 @@ int ldp_server_create(ldp_server **out, const ldp_server_config *cfg)
     const ldp_server_config c = *cfg;
     if (c.pool_bytes < 4096 || c.max_inflight < 1 || c.max_batch < 1 || c.depth < 1 ||
         c.depth > 8 || c.k < 1 || c.k > 8 || c.cells_y < 1 || c.cells_x < 1 ||
-        c.cells_x > ldp::kMaxFusedCellsX || c.dry_run_us < 0)
+        c.cells_y > LDP_MAX_SIDE - 2 || c.cells_x > LDP_MAX_SIDE - 2 || c.dry_run_us < 0)
         return LDP_ERR_INVALID_ARG;
     ldp_server *s = new (std::nothrow) ldp_server();
     if (!s)
@@ -343,8 +348,12 @@ int ldp_server_create(ldp_server **out, const ldp_server_config *cfg)
             }
             s->streams.push_back(st);
             s->events.push_back(ev);
-            int rc = ldp_batch_plan_create(&p, c.max_batch, c.pool_bytes, c.k, c.cells_y,
-                                           c.cells_x, &kServeTune);
+            // pixel capacity independent of the pool: images read in place
+            // take no pool space, so a batch's pixels are bounded only by
+            // max_batch images of the largest side
+            const int64_t max_px = (int64_t)c.max_batch * LDP_MAX_SIDE * LDP_MAX_SIDE;
+            int rc = ldp_batch_plan_create(&p, c.max_batch, max_px, c.k, c.cells_y, c.cells_x,
+                                           &kServeTune);
             if (rc != LDP_OK) {
                 release_server(s);
                 return rc;

@@ -66,7 +66,8 @@ def test_invalid_arguments_return_before_any_launch(lib):
     plan = ctypes.c_void_p()
     assert lib.ldp_batch_plan_create(ctypes.byref(plan), 0, 100, 3, 7, 6, None) == E
     assert lib.ldp_batch_plan_create(ctypes.byref(plan), 10, 100, 9, 7, 6, None) == E
-    assert lib.ldp_batch_plan_create(ctypes.byref(plan), 10, 100, 3, 7, 200, None) == E
+    assert lib.ldp_batch_plan_create(ctypes.byref(plan), 10, 100, 3, 7, 70000, None) == E
+    assert lib.ldp_batch_plan_create(ctypes.byref(plan), 1 << 30, 100, 3, 7, 6, None) == E
     for th in (300, 32, 1088):  # not a whole number of waves, or above 1024
         t = binding.make_tune(dict(block_threads=th))
         assert lib.ldp_batch_plan_create(ctypes.byref(plan), 10, 100, 3, 7, 6, ctypes.byref(t)) == E
@@ -90,8 +91,8 @@ def test_invalid_arguments_return_before_any_launch(lib):
     assert lib.ldp_extract_windows(p, 10, 10, 10, 3, 8, 2, 2, p, p, None) == E
     assert lib.ldp_histograms_windows(p, 10, 10, 0, 1, p, None) == E
     assert lib.ldp_batch_plan_create_windows(ctypes.byref(plan), 10, 100, 2, 3, 0, 5, 5, None) == E
-    assert (lib.ldp_batch_plan_create_windows(ctypes.byref(plan), 10, 10 ** 6, 1000, 3, 0, 5, 5,
-                                              None) == binding.LDP_ERR_UNSUPPORTED)  # 200 windows
+    assert lib.ldp_batch_plan_create_windows(ctypes.byref(plan), 10, 10 ** 6, 70000, 3, 0, 5, 5,
+                                             None) == E
     assert lib.ldp_stream_copy(p, p, -1, None) == E
     assert lib.ldp_stream_copy(None, p, 16, None) == E
     assert lib.ldp_stream_copy(p, None, 16, None) == E

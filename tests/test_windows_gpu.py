@@ -31,7 +31,7 @@ def _dev(a):
                                  (1, 1), (500, 3), (3, 700)])
 def test_window_extract_matches_oracle(lib, win):
     """280x280 (Table 3's geometry), the 490x640 frame (10-px windows give 64
-    columns: the two-pass path) and a small odd image."""
+    columns: two runs of cells per cell row) and a small odd image."""
     for img in [synth.image(synth.KIND_BLUR_RECTS, 12, 0, 280, 280),
                 synth.workload_image("single", 0),
                 synth.image(synth.KIND_BLUR_SP_FLAT, 13, 1, 37, 51)]:
@@ -50,9 +50,11 @@ def test_window_extract_without_codes(lib):
     _, h = lib.extract_windows(_dev(img), 3, 10, 10, want_codes=False)
     wh = oracle_np.window_histograms(oracle_c.ldp_codes(img, 3), 10, 10)
     assert (h.cpu().numpy().view(np.uint32) == wh).all()
-    big = synth.workload_image("single", 0)  # 64 window columns need the code map
-    with pytest.raises(lib.LdpError):
-        lib.extract_windows(_dev(big), 3, 10, 10, want_codes=False)
+    big = synth.workload_image("single", 0)  # 64 window columns: two runs of 32
+    for win in ((10, 10), (1, 1), (3, 5)):
+        _, h = lib.extract_windows(_dev(big), 3, *win, want_codes=False)
+        wh = oracle_np.window_histograms(oracle_c.ldp_codes(big, 3), *win)
+        assert (h.cpu().numpy().view(np.uint32) == wh).all(), win
 
 
 class WinBatch:
@@ -126,4 +128,62 @@ def test_window_plan_grows_its_item_table_and_rejects_wide_images(lib):
     wide = WinBatch([50], [300], synth.KIND_BLUR_RECTS, 94, win)
     with pytest.raises(lib.LdpError):
         plan.set(lib.BatchPlan.descs(*wide.args))
+    plan.close()
+
+
+@pytest.mark.parametrize("win", [(10, 10), (7, 3), (2, 1)])
+def test_window_plan_rows_wider_than_63_windows(lib, win):
+    """Table 3's 10x10 windows on 640-wide frames (64 window columns) and finer
+    grids (up to 638 windows a row) in a batch plan: each cell row is cut into
+    runs of at most 63 windows over several work items; images of other widths
+    in the same batch take their own runs."""
+    r = np.random.default_rng(95)
+    n = 24
+    Hs, Ws = r.integers(3, 500, n), r.integers(3, 641, n)
+    Hs[:4], Ws[:4] = [490, 490, 100, 12], [640, 640, 639, 400]
+    b = WinBatch(Hs, Ws, synth.KIND_BLUR_RECTS, 96, win)
+    pixels = int((b.Hs.astype(np.int64) * b.Ws).sum())
+    plan = lib.BatchPlan(n, pixels, 3, *win, windows=True, max_width=640)
+    plan.set(lib.BatchPlan.descs(*b.args))
+    plan.run()
+    plan.run()
+    torch.cuda.synchronize()
+    for j in range(n):
+        wc = oracle_c.ldp_codes(b.image(j), 3)
+        assert (b.codes[j].cpu().numpy().reshape(wc.shape) == wc).all(), j
+        assert (b.hist[j].cpu().numpy().view(np.uint32) == oracle_np.window_histograms(wc, *win)).all(), j
+    plan.close()
+
+
+@pytest.mark.parametrize("cells_x", [64, 100, 130])
+def test_cell_plan_more_than_63_cell_columns(lib, cells_x):
+    """Cell grids wider than one workgroup's LDS row, in batch plans and in the
+    single-image call without a code map."""
+    r = np.random.default_rng(97 + cells_x)
+    n = 10
+    Hs, Ws = r.integers(20, 300, n), r.integers(cells_x + 2, 900, n)
+    off, strides, total = synth.layout(Hs, Ws)
+    host = np.zeros(total + 64, np.uint8)
+    synth.fill(host, off, Hs, Ws, strides, synth.KIND_BLUR_SP_FLAT, 98)
+    dev = torch.from_numpy(host).cuda()
+    grid = (3, cells_x)
+    codes = [torch.empty((int(h) - 2) * (int(w) - 2), dtype=torch.uint8, device="cuda")
+             for h, w in zip(Hs, Ws)]
+    hists = [torch.full(grid + (256,), 7, dtype=torch.int32, device="cuda") for _ in range(n)]
+    plan = lib.BatchPlan(n, int((Hs.astype(np.int64) * Ws).sum()), 3, *grid)
+    plan.set(lib.BatchPlan.descs([dev.data_ptr() + int(o) for o in off],
+                                 [c.data_ptr() for c in codes], [h.data_ptr() for h in hists],
+                                 [int(s) for s in strides], [int(h) for h in Hs],
+                                 [int(w) for w in Ws]))
+    plan.run()
+    torch.cuda.synchronize()
+    for j in range(n):
+        H, W, s, o = int(Hs[j]), int(Ws[j]), int(strides[j]), int(off[j])
+        img = host[o:o + H * s].reshape(H, s)[:, :W]
+        wc = oracle_c.ldp_codes(img, 3)
+        wh = oracle_c.ldp_histograms(wc, *grid)
+        assert (codes[j].cpu().numpy().reshape(wc.shape) == wc).all(), j
+        assert (hists[j].cpu().numpy().view(np.uint32) == wh).all(), j
+        _, h1 = lib.extract(_dev(img), 3, *grid, want_codes=False)
+        assert (h1.cpu().numpy().view(np.uint32) == wh).all(), j
     plan.close()
