@@ -334,6 +334,8 @@ typedef struct ldp_completion {
 
 typedef struct ldp_server_stats {
     int64_t submitted, completed, rejected, launches;
+    int64_t memory_waits;     /* requests that reached the head of the queue and
+                               * waited there for pool memory */
     int64_t peak_pool_bytes;  /* most pool bytes in use at once */
     int32_t peak_inflight;    /* most requests admitted at once */
     int32_t peak_batches;     /* most launches in flight at once */

@@ -96,7 +96,7 @@ class Completion(ctypes.Structure):
 class ServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
                 ("rejected", ctypes.c_int64), ("launches", ctypes.c_int64),
-                ("peak_pool_bytes", ctypes.c_int64), ("peak_inflight", ctypes.c_int32),
+                ("memory_waits", ctypes.c_int64), ("peak_pool_bytes", ctypes.c_int64), ("peak_inflight", ctypes.c_int32),
                 ("peak_batches", ctypes.c_int32), ("max_batch_seen", ctypes.c_int32),
                 ("waiting", ctypes.c_int32)]
 

@@ -94,6 +94,7 @@ struct Req {
     const uint8_t *img_dev = nullptr;
     double t_submit, t_admit = 0;
     int64_t off = -1, bytes = 0, img_bytes = 0, code_bytes = 0;
+    bool waited_for_memory = false;
 };
 
 struct Batch {
@@ -241,8 +242,14 @@ void dispatcher(ldp_server *s)
                 // requests whose buffers are all read and written in place
                 // need no pool space
                 const int64_t off = r->bytes ? s->pool->alloc(r->bytes) : 0;
-                if (off < 0)
-                    break;  // head of line waits for memory
+                if (off < 0) {
+                    // head of line waits for memory
+                    if (!r->waited_for_memory) {
+                        r->waited_for_memory = true;
+                        s->st.memory_waits += 1;
+                    }
+                    break;
+                }
                 r->off = off;
                 r->t_admit = now_s();
                 s->pending.pop_front();

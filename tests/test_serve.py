@@ -65,6 +65,7 @@ def test_requests_that_do_not_fit_wait_instead_of_failing():
     srv.close()
     assert len(done) == 6 and st["peak_inflight"] == 1 and st["max_batch_seen"] == 1
     assert st["launches"] == 6
+    assert st["memory_waits"] == 5      # each later request waited at the head of the queue
     done.sort(key=lambda d: d["id"])
     for a, b in zip(done, done[1:]):
         assert b["t_admit"] >= a["t_done"]  # admitted only once memory came back
