@@ -281,6 +281,26 @@ int ldp_batch_run(ldp_batch_plan *plan, ldp_stream_t stream);
 int ldp_batch_launch(ldp_batch_plan *plan, const ldp_image_desc *descs, int32_t n,
                      ldp_stream_t stream);
 
+/*
+ * ldp_batch_launch_noalloc -- for callers that cannot allocate memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation.  Runs a small batch like ldp_batch_launch on a plan for cells
+ * (flags 0): each image gets ldp_extract's codes (when `codes` is not NULL)
+ * and cells_y x cells_x histograms for k.  No plan: the batch travels in the
+ * kernel's arguments and the work-queue words live in a fixed 256-byte device
+ * array of the library, one per GPU, kept until the process ends.  The call
+ * allocates nothing, host or device (the first call on a GPU also clears that
+ * GPU's array with a small kernel on `stream`).  Limits: at most
+ * LDP_ARG_BATCH_IMAGES images and LDP_ARG_BATCH_ITEMS work items (one item
+ * per cell row, per run of at most 63 cells of it); larger batches return
+ * LDP_ERR_UNSUPPORTED and launch nothing.  Every call on one GPU shares its
+ * queue words: calls that overlap on one GPU (different streams without
+ * ordering) race and give wrong results; order them.  Other errors as
+ * ldp_batch_launch (LDP_ERR_INVALID_ARG for a bad image, k or grid).
+ */
+int ldp_batch_launch_noalloc(const ldp_image_desc *descs, int32_t n, int32_t k, int32_t cells_y,
+                             int32_t cells_x, ldp_stream_t stream);
+
 /* ldp_batch_run_per_image -- the same batch as one ldp_extract launch per
  * image, for comparison with the persistent launch. */
 int ldp_batch_run_per_image(ldp_batch_plan *plan, ldp_stream_t stream);

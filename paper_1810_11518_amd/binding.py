@@ -34,7 +34,7 @@ EXPORTED = [
     "ldp_batch_plan_set", "ldp_batch_run", "ldp_batch_launch", "ldp_batch_run_per_image",
     "ldp_batch_plan_info", "ldp_batch_plan_destroy",
     "ldp_now", "ldp_server_create", "ldp_server_submit", "ldp_server_poll",
-    "ldp_server_stats_get", "ldp_server_destroy", "ldp_stream_copy",
+    "ldp_server_stats_get", "ldp_server_destroy", "ldp_stream_copy", "ldp_batch_launch_noalloc",
 ]
 
 
@@ -155,6 +155,8 @@ def load():
         "ldp_server_stats_get": (ctypes.c_int, [p, ctypes.POINTER(ServerStats)]),
         "ldp_server_destroy": (ctypes.c_int, [p]),
         "ldp_stream_copy": (ctypes.c_int, [p, p, i64, p]),
+        "ldp_batch_launch_noalloc": (ctypes.c_int, [ctypes.POINTER(ImageDesc), i32, i32, i32, i32,
+                                                    p]),
     }
     for name, (res, args) in sig.items():
         if not hasattr(lib, name):
@@ -299,6 +301,13 @@ def compact_histograms(hist, k, out=None, stream=None):
     _check(load().ldp_compact_histograms(hist.data_ptr(), n_cells, k, out.data_ptr(),
                                          _stream(stream)), "ldp_compact_histograms")
     return out
+
+
+def batch_launch_noalloc(descs, k, cells_y, cells_x, stream=None):
+    """ldp_batch_launch_noalloc: a small batch (ctypes ImageDesc array, see
+    BatchPlan.descs) with no plan and no allocation."""
+    _check(load().ldp_batch_launch_noalloc(descs, len(descs), k, cells_y, cells_x,
+                                           _stream(stream)), "ldp_batch_launch_noalloc")
 
 
 def stream_copy(src, dst, stream=None):

@@ -13,6 +13,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <vector>
@@ -695,3 +696,156 @@ int run_batch(ldp_batch_plan *p, const ldp_image_desc *descs, int32_t n, hipStre
     return rc == LDP_OK ? ldp_batch_run(p, (ldp_stream_t)s) : rc;
 }
 }  // namespace ldp
+
+// ---------------------------------------------------------------- no allocation
+// ldp_batch_launch_noalloc: the argument-table launch of ldp_batch_launch with
+// its work-queue words in a file-scope device array instead of a plan's
+// allocation.  Each device holds its own copy of the array until the process
+// ends; the host reaches it through the address hipGetSymbolAddress returns
+// with that device current (the array's name is not a device address in host
+// code), taken once per device and kept.
+namespace ldp {
+namespace {
+
+constexpr int kScratchBytes = 256;  // the queue words (Meta), padded
+static_assert(sizeof(Meta) <= kScratchBytes, "queue words fit the scratch array");
+constexpr int kMaxDevices = 64;
+// Launch shape for these small batches (as the server's): one cell row per
+// work item, lane tasks of >= 4 rows, 1024-thread workgroups.
+constexpr int kNoallocThreads = 1024;
+constexpr int32_t kNoallocTaskRows = 4;
+
+__global__ void clear_words_kernel(uint32_t *p, int32_t n)
+{
+    for (int32_t i = threadIdx.x; i < n; i += blockDim.x)
+        p[i] = 0u;
+}
+
+std::mutex g_scratch_mu;
+Meta *g_scratch[kMaxDevices] = {};
+
+}  // namespace
+}  // namespace ldp
+
+static __device__ __align__(256) unsigned char scratch[ldp::kScratchBytes];
+
+namespace ldp {
+namespace {
+
+// The device address of this device's scratch array; on the first call for a
+// device its words are cleared by a kernel on `s` (ahead of any launch the
+// caller then makes on `s`).
+int scratch_for(int dev, hipStream_t s, Meta **out)
+{
+    if (dev < 0 || dev >= kMaxDevices)
+        return LDP_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr)
+            return LDP_ERR_HIP;
+        hipLaunchKernelGGL(clear_words_kernel, dim3(1), dim3(64), 0, s,
+                           reinterpret_cast<uint32_t *>(ptr), kScratchBytes / 4);
+        if (hipGetLastError() != hipSuccess)
+            return LDP_ERR_HIP;
+        g_scratch[dev] = reinterpret_cast<Meta *>(ptr);
+    }
+    *out = g_scratch[dev];
+    return LDP_OK;
+}
+
+// Work items of a batch for the argument table, in fixed-size storage (no
+// heap): one cell row per item, each cell row cut into runs of at most 63
+// cells, largest first.  Errors as ldp_batch_launch, and LDP_ERR_UNSUPPORTED
+// past LDP_ARG_BATCH_IMAGES images or LDP_ARG_BATCH_ITEMS items.
+int cut_items_fixed(const ldp_image_desc *descs, int32_t n, int32_t gy, int32_t gx, ArgBatch &b,
+                    int32_t &run_cells)
+{
+    if (n > kArgImages)
+        return LDP_ERR_UNSUPPORTED;
+    const int32_t runs = cell_runs(gx);
+    run_cells = (gx + runs - 1) / runs;
+    int64_t size[kArgItems];
+    int32_t m = 0;
+    for (int32_t j = 0; j < n; ++j) {
+        const ldp_image_desc &d = descs[j];
+        const int st = check_image(d.img, d.H, d.W, d.stride);
+        if (st != LDP_OK)
+            return st;
+        if (!d.hist || d.H - 2 < gy || d.W - 2 < gx)
+            return LDP_ERR_INVALID_ARG;
+    }
+    for (int32_t j = 0; j < n; ++j) {
+        const ldp_image_desc &d = descs[j];
+        const int32_t Hc = d.H - 2, Wc = d.W - 2;
+        const Geom geo = make_geom(Hc, Wc, gy, gx, false);
+        for (int32_t cy = 0; cy < geo.ny; ++cy) {
+            const int64_t rows = geom_row_start(geo, cy + 1, Hc) - geom_row_start(geo, cy, Hc);
+            for (int32_t xi = 0; xi < runs; ++xi) {
+                if (m == kArgItems)
+                    return LDP_ERR_UNSUPPORTED;
+                const int32_t cx0 = cell_run_start(geo.nx, runs, xi);
+                const int32_t cx1 = cell_run_start(geo.nx, runs, xi + 1);
+                const Item it{(uint32_t)j, (uint16_t)cy, (uint16_t)(cy + 1), (uint16_t)cx0,
+                              (uint16_t)cx1};
+                const int64_t sz = rows * (geom_col_start(geo, cx1, Wc) -
+                                           geom_col_start(geo, cx0, Wc));
+                // insertion, largest first (stable)
+                int32_t at = m;
+                while (at > 0 && size[at - 1] < sz) {
+                    b.items[at] = b.items[at - 1];
+                    size[at] = size[at - 1];
+                    --at;
+                }
+                b.items[at] = it;
+                size[at] = sz;
+                ++m;
+            }
+        }
+    }
+    b.n_items = (uint32_t)m;
+    for (int32_t j = 0; j < n; ++j)
+        b.descs[j] = descs[j];
+    return LDP_OK;
+}
+
+}  // namespace
+}  // namespace ldp
+
+extern "C" int ldp_batch_launch_noalloc(const ldp_image_desc *descs, int32_t n, int32_t k,
+                                        int32_t cells_y, int32_t cells_x, ldp_stream_t stream)
+{
+    using namespace ldp;
+    if (n < 0 || (n > 0 && !descs) || k < 1 || k > 8 || cells_y < 1 || cells_x < 1 ||
+        cells_y > LDP_MAX_SIDE - 2 || cells_x > LDP_MAX_SIDE - 2)
+        return LDP_ERR_INVALID_ARG;
+    ArgBatch b{};
+    int32_t run_cells = 1;
+    int rc = cut_items_fixed(descs, n, cells_y, cells_x, b, run_cells);
+    if (rc != LDP_OK)
+        return rc;
+    if (b.n_items == 0)
+        return LDP_OK;
+    hipStream_t s = (hipStream_t)stream;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return LDP_ERR_HIP;
+    Meta *meta = nullptr;
+    rc = scratch_for(dev, s, &meta);
+    if (rc != LDP_OK)
+        return rc;
+    // one cell row of histograms per item, then the item broadcast word
+    const size_t hist_bytes = hist_row_bytes(run_cells);
+    const size_t lds_bytes = hist_bytes + 16;
+    int32_t gy = cells_y, gx = cells_x, windows = 0;
+    int32_t item_slot = (int32_t)(hist_bytes / 4);
+    MinRows min_rows{{kNoallocTaskRows, kNoallocTaskRows, kNoallocTaskRows, kNoallocTaskRows}};
+    void *args[] = {&b, &meta, &gy, &gx, &windows, &item_slot, &min_rows};
+    // no more workgroups than items: each takes items until the queue is
+    // empty, and the last one out leaves the queue words at zero
+    const batch_arg_fn fn = batch_arg_kernel_for(k);
+    return hipLaunchKernel(reinterpret_cast<const void *>(fn), dim3(b.n_items),
+                           dim3(kNoallocThreads), args, lds_bytes, s) == hipSuccess
+               ? LDP_OK
+               : LDP_ERR_HIP;
+}

@@ -93,6 +93,17 @@ def test_invalid_arguments_return_before_any_launch(lib):
     assert lib.ldp_batch_plan_create_windows(ctypes.byref(plan), 10, 100, 2, 3, 0, 5, 5, None) == E
     assert lib.ldp_batch_plan_create_windows(ctypes.byref(plan), 10, 10 ** 6, 70000, 3, 0, 5, 5,
                                              None) == E
+    descs = (binding.ImageDesc * 29)()
+    for d in descs:
+        d.img, d.hist, d.stride, d.H, d.W = 0x1000, 0x2000, 40, 40, 40
+    assert lib.ldp_batch_launch_noalloc(descs, -1, 3, 7, 6, None) == E
+    assert lib.ldp_batch_launch_noalloc(None, 3, 3, 7, 6, None) == E
+    assert lib.ldp_batch_launch_noalloc(descs, 3, 0, 7, 6, None) == E
+    assert lib.ldp_batch_launch_noalloc(descs, 3, 3, 0, 6, None) == E
+    assert lib.ldp_batch_launch_noalloc(descs, 3, 3, 7, 39, None) == E       # W - 2 < cells_x
+    assert lib.ldp_batch_launch_noalloc(descs, 29, 3, 7, 6, None) == binding.LDP_ERR_UNSUPPORTED
+    assert lib.ldp_batch_launch_noalloc(descs, 28, 3, 8, 6, None) == binding.LDP_ERR_UNSUPPORTED
+    assert lib.ldp_batch_launch_noalloc(descs, 0, 3, 7, 6, None) == binding.LDP_OK  # nothing to do
     assert lib.ldp_stream_copy(p, p, -1, None) == E
     assert lib.ldp_stream_copy(None, p, 16, None) == E
     assert lib.ldp_stream_copy(p, None, 16, None) == E
