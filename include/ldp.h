@@ -309,7 +309,8 @@ int ldp_batch_run_per_image(ldp_batch_plan *plan, ldp_stream_t stream);
  * batch (either pointer may be NULL). */
 int ldp_batch_plan_info(const ldp_batch_plan *plan, int64_t *work_items, int32_t *grid_blocks);
 
-/* ldp_batch_plan_destroy -- release the plan (waits for its device work). */
+/* ldp_batch_plan_destroy -- release the plan (waits for the plan's last
+ * launch and last upload, not for other work on the device). */
 int ldp_batch_plan_destroy(ldp_batch_plan *plan);
 
 /* ---------------------------------------------------------------- serving

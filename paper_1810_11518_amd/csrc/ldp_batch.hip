@@ -250,6 +250,10 @@ struct ldp_batch_plan {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipEvent_t uploaded = nullptr;
+    // recorded after every launch of the plan (launches on one plan are
+    // ordered: they share its queue), so that a table the plan replaces or
+    // frees is released only once the last launch that can read it has ended
+    hipEvent_t ran = nullptr;
 };
 
 namespace {
@@ -262,6 +266,7 @@ void release(ldp_batch_plan *p)
     if (p->graph) (void)hipGraphDestroy(p->graph);
     if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
     if (p->uploaded) (void)hipEventDestroy(p->uploaded);
+    if (p->ran) (void)hipEventDestroy(p->ran);
     if (!p->items_in_block) {
         if (p->d_items) (void)hipFree(p->d_items);
         if (p->h_items) (void)hipHostFree(p->h_items);
@@ -389,7 +394,8 @@ int create_plan(ldp_batch_plan **out, int32_t max_images, int64_t max_pixels, in
         p->grid = std::max(1, per_cu) * std::max(1, cus);
     }
     if (hipStreamCreate(&p->cap_stream) != hipSuccess ||
-        hipEventCreateWithFlags(&p->uploaded, hipEventDisableTiming) != hipSuccess)
+        hipEventCreateWithFlags(&p->uploaded, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&p->ran, hipEventDisableTiming) != hipSuccess)
         return fail(LDP_ERR_HIP);
     // capture: the persistent kernel (it leaves its queue reset for the next
     // launch)
@@ -541,8 +547,9 @@ int ldp_batch_plan_set(ldp_batch_plan *p, const ldp_image_desc *descs, int32_t n
             (void)hipFree(d);
             return LDP_ERR_NO_MEMORY;
         }
-        // the old table may still feed a launch in flight
-        if (hipDeviceSynchronize() != hipSuccess) {
+        // the old table may still feed a launch in flight: wait for the
+        // plan's last launch (not the whole device)
+        if (hipEventSynchronize(p->ran) != hipSuccess) {
             (void)hipFree(d);
             (void)hipHostFree(h);
             return LDP_ERR_HIP;
@@ -590,7 +597,10 @@ int ldp_batch_run(ldp_batch_plan *p, ldp_stream_t stream)
         return LDP_ERR_INVALID_ARG;
     if (p->n_items == 0)
         return LDP_OK;
-    return hipGraphLaunch(p->exec, (hipStream_t)stream) == hipSuccess ? LDP_OK : LDP_ERR_HIP;
+    return hipGraphLaunch(p->exec, (hipStream_t)stream) == hipSuccess &&
+                   hipEventRecord(p->ran, (hipStream_t)stream) == hipSuccess
+               ? LDP_OK
+               : LDP_ERR_HIP;
 }
 
 int ldp_batch_run_per_image(ldp_batch_plan *p, ldp_stream_t stream)
@@ -603,7 +613,7 @@ int ldp_batch_run_per_image(ldp_batch_plan *p, ldp_stream_t stream)
         if (st != LDP_OK)
             return st;
     }
-    return LDP_OK;
+    return hipEventRecord(p->ran, (hipStream_t)stream) == hipSuccess ? LDP_OK : LDP_ERR_HIP;
 }
 
 int ldp_batch_plan_info(const ldp_batch_plan *p, int64_t *work_items, int32_t *grid_blocks)
@@ -621,7 +631,11 @@ int ldp_batch_plan_destroy(ldp_batch_plan *p)
 {
     if (!p)
         return LDP_ERR_INVALID_ARG;
-    (void)hipDeviceSynchronize();
+    // the plan's last launch and last upload (other streams run on)
+    if (p->ran)
+        (void)hipEventSynchronize(p->ran);
+    if (p->uploaded)
+        (void)hipEventSynchronize(p->uploaded);
     release(p);
     return LDP_OK;
 }
@@ -650,7 +664,8 @@ int launch_args(const ldp_batch_plan *p, batch_arg_fn fn, ArgBatch &b, hipStream
     MinRows min_rows = p->min_rows;
     void *args[] = {&b, &meta, &gy, &gx, &windows, &item_slot, &min_rows};
     return hipLaunchKernel(reinterpret_cast<const void *>(fn), dim3(grid), dim3(p->threads), args,
-                           p->lds_bytes, s) == hipSuccess
+                           p->lds_bytes, s) == hipSuccess &&
+                   hipEventRecord(p->ran, s) == hipSuccess
                ? LDP_OK
                : LDP_ERR_HIP;
 }

@@ -190,3 +190,26 @@ def test_burst_behind_a_large_image_then_single_requests(lib):
     for img, hist in zip(imgs, outs):
         _, want = oracle_c.ldp_extract(img, 3, *cells)
         assert (hist.reshape(want.shape) == want).all(), img.shape
+
+
+def test_in_place_batches_larger_than_the_pool(lib):
+    """Page-locked images and histograms take no pool space, so a batch of
+    them may hold far more pixels than the pool has bytes: every request
+    still completes with status 0 and the oracle's histograms."""
+    pool = 64 << 10
+    srv = lib.Server(pool, max_inflight=64, max_batch=32, depth=1, k=3, cells_y=7, cells_x=6)
+    reqs = _requests(24, 23)          # ~ 24 x 0.25 M pixels, against a 64 KiB pool
+    assert sum(img.size for _, img in reqs) > 20 * pool
+    hists = []
+    for keep, img in reqs:
+        k, hist = _pinned((7 * 6 * 256,), np.uint32)
+        hist[:] = 7
+        hists.append((k, hist))
+        srv.submit(img, hist)
+    done = _drain(srv, len(reqs))
+    st = srv.stats()
+    srv.close()
+    assert all(d["status"] == 0 for d in done)
+    assert st["peak_pool_bytes"] == 0 and st["max_batch_seen"] >= 1
+    for (keep, img), (k, hist) in zip(reqs, hists):
+        assert (hist.reshape(7, 6, 256) == oracle_c.ldp_extract(img, 3, 7, 6)[1]).all()
