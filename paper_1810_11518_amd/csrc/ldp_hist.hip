@@ -4,8 +4,8 @@
 // many cells for one workgroup's LDS.
 //
 // A workgroup takes one work item: the code rows [r0, r1) of one cell row
-// and the cells [cx0, cx1) of that row (at most kMaxFusedCellsX of them, so
-// their bins fit in LDS with one discard cell).  A lane owns a chunk of 16
+// and the cells [cx0, cx1) of that row (at most kItemCells of them, so their
+// bins fit in LDS with one discard cell).  A lane owns a chunk of 16
 // adjacent code columns and a band of the item's rows.  It finds the LDS cell
 // of each of its 16 columns once, then walks its rows: 16 codes per row
 // (five dword loads from the 4-aligned offset at or below them, realigned;
@@ -16,6 +16,11 @@
 // The last chunk of a column range is moved left to end at the range's last
 // column; the columns it shares with the previous chunk (counted there) go to
 // the discard cell, as do the columns past a range narrower than 16.
+//
+// Every bin is held kCopies times in neighbouring LDS words, lane l adding to
+// copy l % kCopies: codes repeat across nearby columns, and lanes adding to
+// the same LDS word are serialised, so the copies cut that contention
+// kCopies-fold; the flush sums them.
 #include "ldp_engine.hpp"
 #include "ldp_host.hpp"
 
@@ -23,7 +28,25 @@ namespace ldp {
 
 namespace {
 
-constexpr int kChunk = 16;  // code columns per lane
+constexpr int kChunk = 16;    // code columns per lane
+constexpr int kCopies = 4;    // LDS copies of every bin
+constexpr int kItemCells = 7; // cells of a cell row per item: (7 + 1) x 4 KiB of LDS
+
+// LDS byte address of the bin of the (code, cell) pair in one 16-bit half of
+// `pr`: half * 4 * kCopies + the lane's base (its copy), one v_mad_u32_u16.
+__device__ __forceinline__ uint32_t cbin_lo(uint32_t pr, uint32_t base)
+{
+    uint32_t r;
+    asm("v_mad_u32_u16 %0, %1, 16, %2" : "=v"(r) : "v"(pr), "v"(base));
+    return r;
+}
+__device__ __forceinline__ uint32_t cbin_hi(uint32_t pr, uint32_t base)
+{
+    uint32_t r;
+    asm("v_mad_u32_u16 %0, %1, 16, %2 op_sel:[1,0,0,0]" : "=v"(r) : "v"(pr), "v"(base));
+    return r;
+}
+static_assert(kCopies == 4, "cbin_lo/cbin_hi multiply by 4 * kCopies = 16");
 
 __global__ void hist_zero_kernel(uint32_t *__restrict__ p, int64_t n)
 {
@@ -55,13 +78,14 @@ __device__ __forceinline__ void load_codes(uint32_t (&q)[4], __amdgpu_buffer_rsr
 }
 
 // Count one row of 16 codes: q holds the codes, d the LDS cell of each
-// column in the same byte positions.
+// column in the same byte positions; `base` is the LDS address of the lane's
+// bin copy.
 __device__ __forceinline__ void count_row(const uint32_t (&q)[4], const uint32_t (&d)[4],
                                           bool uniform_cell, uint32_t base)
 {
     if (uniform_cell && q[0] == q[1] && q[0] == q[2] && q[0] == q[3] &&
         q[0] == __builtin_amdgcn_alignbyte(q[0], q[0], 1)) {
-        lds_count(bin_lo(bin_pair(q[0], d[0], 0, 1), base), 16u);
+        lds_count(cbin_lo(bin_pair(q[0], d[0], 0, 1), base), 16u);
         return;
     }
 #pragma unroll
@@ -69,8 +93,8 @@ __device__ __forceinline__ void count_row(const uint32_t (&q)[4], const uint32_t
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const uint32_t pr = bin_pair(q[i], d[i], 2 * h, 2 * h + 1);
-            lds_count(bin_lo(pr, base), 1u);
-            lds_count(bin_hi(pr, base), 1u);
+            lds_count(cbin_lo(pr, base), 1u);
+            lds_count(cbin_hi(pr, base), 1u);
         }
     }
 }
@@ -112,7 +136,7 @@ __global__ void __launch_bounds__(1024) hist_kernel(const uint8_t *__restrict__ 
     const int32_t c_lo = geom_col_start(geo, cx0, Wc), c_hi = geom_col_start(geo, cx1, Wc);
 
     uint4 *lds4 = reinterpret_cast<uint4 *>(lds);
-    for (int32_t i = tid; i < (ncell + 1) * 64; i += nthreads)
+    for (int32_t i = tid; i < (ncell + 1) * 64 * kCopies; i += nthreads)
         lds4[i] = make_uint4(0u, 0u, 0u, 0u);
     __syncthreads();
 
@@ -124,7 +148,7 @@ __global__ void __launch_bounds__(1024) hist_kernel(const uint8_t *__restrict__ 
     const int64_t extent = (int64_t)off0 + (int64_t)(r1 - r0) * Wc;
     const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
         (void *)pbase, (short)0, (int)((extent + 3) & ~(int64_t)3), 0x00020000);
-    const uint32_t base = lds_base(lds);
+    const uint32_t base = lds_base(lds) + 4u * (uint32_t)(tid % kCopies);
 
     const int32_t width = c_hi - c_lo, rows = r1 - r0;
     const int32_t nchunks = (width + kChunk - 1) / kChunk;
@@ -165,7 +189,8 @@ __global__ void __launch_bounds__(1024) hist_kernel(const uint8_t *__restrict__ 
     typedef __attribute__((address_space(1))) uint32_t global_u32;
     global_u32 *dst = (global_u32 *)(hist + ((int64_t)cy * geo.nx + cx0) * 256);
     for (int32_t i = tid; i < ncell * 256; i += nthreads) {
-        const uint32_t v = lds[i];
+        const uint4 c = lds4[i];  // the kCopies copies of bin i
+        const uint32_t v = c.x + c.y + c.z + c.w;
         if (split == 1)
             dst[i] = v;
         else if (v)
@@ -180,7 +205,7 @@ int launch_histograms(const uint8_t *codes, int32_t H, int32_t W, int32_t gy, in
 {
     const int32_t Hc = H - 2, Wc = W - 2;
     const Geom geo = make_geom(Hc, Wc, gy, gx, windows);
-    const int32_t cpi = std::min<int32_t>(geo.nx, kMaxFusedCellsX);
+    const int32_t cpi = std::min<int32_t>(geo.nx, kItemCells);
     const int32_t nxi = (geo.nx + cpi - 1) / cpi;
     const int64_t items = (int64_t)geo.ny * nxi;
     // columns of the widest item: threads for one 16-column chunk each
@@ -201,7 +226,7 @@ int launch_histograms(const uint8_t *codes, int32_t H, int32_t W, int32_t gy, in
                            dim3((unsigned)std::min<int64_t>((n + 255) / 256, 1024)), dim3(256), 0,
                            s, hist, n);
     }
-    const size_t lds = (size_t)(cpi + 1) * 1024;
+    const size_t lds = (size_t)(cpi + 1) * 1024 * kCopies;
     hipLaunchKernelGGL(hist_kernel, dim3((unsigned)(items * split)), dim3(threads), lds, s, codes,
                        Hc, Wc, geo, cpi, (int32_t)split, min_band, hist);
     return hipGetLastError() == hipSuccess ? LDP_OK : LDP_ERR_HIP;
