@@ -101,3 +101,34 @@ def test_noalloc_refuses_batches_past_its_limits(lib):
     with pytest.raises(lib.LdpError) as e:        # 28 x 8 = 224 work items
         lib.batch_launch_noalloc(few, 3, 8, 6)
     assert e.value.status == lib.LDP_ERR_UNSUPPORTED
+
+
+def test_noalloc_replays_under_graph_capture(lib):
+    """The callers it is for: a HIP graph captured around the call, replayed
+    three times with eager work (poisoning the outputs) and synchronisations
+    between the replays; every replay equals the eager call."""
+    cells = (7, 6)
+    Hs = np.array([490, 77, 300], dtype=np.int32)
+    Ws = np.array([640, 130, 411], dtype=np.int32)
+    b = _batch(lib, Hs, Ws, cells, 410)
+    _poison(b)
+    lib.batch_launch_noalloc(b["descs"], 3, *cells)      # eager (first use on this GPU done)
+    torch.cuda.synchronize()
+    want_c, want_h = _outputs(b)
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            lib.batch_launch_noalloc(b["descs"], 3, *cells)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        _poison(b)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        got_c, got_h = _outputs(b)
+        for j in range(len(Hs)):
+            assert (got_c[j] == want_c[j]).all(), (rep, j)
+            assert (got_h[j] == want_h[j]).all(), (rep, j)
