@@ -51,7 +51,8 @@ def test_max_side_codes_and_histograms(lib, k):
         img = _skinny(j, H, W)
         want = oracle_c.ldp_codes(img, k)
         assert (lib.codes(_dev(img), k).cpu().numpy() == want).all(), (H, W, k)
-        # fused path, and for the long rows also the two-pass path (> 63 cell columns)
+        # one run of cells per row, and for the long rows also rows cut into runs
+        # (more than 63 cell columns)
         grids = [(min(7, H - 2), min(6, W - 2))]
         if W == MAX_SIDE:
             grids += [(1, 63), (H - 2, 64)]
@@ -77,8 +78,8 @@ def test_max_side_variants(lib, mode):
 
 
 def test_max_side_windows(lib):
-    """Windows over 65536-long maps: a window grid of 63 columns (one pass),
-    66 columns (codes first, then histograms) and 656 window rows."""
+    """Windows over 65536-long maps: a window grid of 63 columns (one run),
+    66 columns (two runs of 33) and 656 window rows."""
     cases = [((4, MAX_SIDE), (2, 1041)), ((4, MAX_SIDE), (2, 1000)), ((MAX_SIDE, 7), (100, 100)),
              ((MAX_SIDE, 13), (1000, 4))]
     for j, ((H, W), win) in enumerate(cases):
