@@ -93,3 +93,12 @@ def test_large_workload_subset(lib, k):
     Hs, Ws, hist = r[0], r[1], r[7]
     _check_all(*r, k=k)
     _check_mass(Hs, Ws, hist, k)
+
+
+def test_large_workload_full_size_k3(lib):
+    """All 64 images of 8192x8192 (4.3 G pixels), k=3, 16x16 cells, every
+    image against the oracle."""
+    r = _run(lib, "large", 3)
+    Hs, Ws, hist = r[0], r[1], r[7]
+    _check_all(*r, k=3)
+    _check_mass(Hs, Ws, hist, 3)
