@@ -27,7 +27,7 @@
 //     The 8 pixels of a lane are held as four pairs (c, c+4), c = 0..3,
 //     which makes the left and right neighbours of each pair another pair.
 //   * The k-th largest of eight values is a branch-free min/max network
-//     (for k = 3, the sorted top three of each half, merged).
+//     (for k = 3, a median of three values taken from four sorted pairs).
 //   * The code bits are the sign bits of S_i + 0x8000 - t (bit 15 of a field
 //     is set exactly when S_i >= t, and no field can carry): v_perm_b32
 //     gathers four of them into four byte masks at once and v_bitop3_b32
@@ -75,18 +75,23 @@ __device__ __forceinline__ u16x2 vmin3(u16x2 a, u16x2 b, u16x2 c)
 
 // ------------------------------------------------------------ k-th largest
 // Eq. 2's m_k: the k-th element of the eight values in descending order,
-// duplicates kept.  Split into halves A = s0..s3 and B = s4..s7, each sorted
-// as two pairs: A_(1) = max(h0, h1) is A's largest, {mh, ml} = {min(h0, h1),
-// max(l0, l1)} its middle two (A_(2) their max, A_(3) their min) and
-// min(l0, l1) its smallest; likewise B with g, k, nh, nl.  The k-th largest
-// of A u B is max over i + j = k of min(A_(i), B_(j)) (A_(0) = +infinity):
-//   k = 2: max(A_(2), B_(2), min(A_(1), B_(1)))
-//   k = 3: max(A_(3), B_(3), min(A_(1), B_(2)), min(A_(2), B_(1))), where the
-//          last two terms together equal min(max(A_(2), B_(2)), A_(1), B_(1))
-//   k = 4: max(A_(4), B_(4), min(A_(2), B_(2)), min(A_(1), B_(3)),
-//          min(A_(3), B_(1))), the last two equal to
-//          min(max(A_(3), B_(3)), A_(1), B_(1)).
-// The (9-k)-th largest is the k-th smallest: the same network with max and
+// duplicates kept.  The values are first sorted in four pairs: h_j / l_j are
+// the larger / smaller of pair j (h0, h1, g0, g1 and l0, l1, k0, k1).  A pair
+// puts 0, 1 or 2 values at or above any level x, and x is at most the k-th
+// largest exactly when a + o >= k, with o the number of pairs whose larger
+// value reaches x and a the number whose smaller one does (a pair counted in
+// a is counted in o).  Written with min/max (each level test is monotone, so
+// a network right for every level is right for every input):
+//   k = 2: o >= 2 or a >= 1: the largest of the pair minima and the second
+//          largest of the pair maxima;
+//   k = 3: (o >= 2 and a >= 1) or o >= 3: the median of three values, the
+//          second and third largest of the pair maxima and the largest pair
+//          minimum;
+//   k = 4: a >= 2, or a >= 1 and o >= 3, or o = 4.
+// The four pair maxima are ranked as two sorted pairs (x1 >= v from h0, h1;
+// y1 >= z from g0, g1): the largest is max(x1, y1), the second and third are
+// max(min(x1, y1), v, z) and min(x1, y1, max(v, z)), the smallest min(v, z).
+// The (9-k)-th largest is the k-th smallest: the same networks with max and
 // min exchanged (k = 5, 6, 7 from 4, 3, 2).
 template <bool SMALLEST>
 struct Order {
@@ -102,27 +107,38 @@ struct Order {
     }
 };
 
-// k-th largest (SMALLEST = false) or k-th smallest (true) for k = 2, 3, 4
+// k-th largest (SMALLEST = false) or k-th smallest (true) for k = 2, 3, 4:
+// 16, 19 and 24 packed min/max per pixel pair
 template <int K, bool SMALLEST>
 __device__ __forceinline__ u16x2 kth_network(const u16x2 (&s)[8])
 {
     typedef Order<SMALLEST> O;
-    u16x2 h0 = O::hi(s[0], s[1]), l0 = O::lo(s[0], s[1]);
-    u16x2 h1 = O::hi(s[2], s[3]), l1 = O::lo(s[2], s[3]);
-    u16x2 g0 = O::hi(s[4], s[5]), k0 = O::lo(s[4], s[5]);
-    u16x2 g1 = O::hi(s[6], s[7]), k1 = O::lo(s[6], s[7]);
-    u16x2 x1 = O::hi(h0, h1), mh = O::lo(h0, h1), ml = O::hi(l0, l1);
-    u16x2 y1 = O::hi(g0, g1), nh = O::lo(g0, g1), nl = O::hi(k0, k1);
+    const u16x2 h0 = O::hi(s[0], s[1]), l0 = O::lo(s[0], s[1]);
+    const u16x2 h1 = O::hi(s[2], s[3]), l1 = O::lo(s[2], s[3]);
+    const u16x2 g0 = O::hi(s[4], s[5]), k0 = O::lo(s[4], s[5]);
+    const u16x2 g1 = O::hi(s[6], s[7]), k1 = O::lo(s[6], s[7]);
+    const u16x2 x1 = O::hi(h0, h1), v = O::lo(h0, h1);
+    const u16x2 y1 = O::hi(g0, g1), z = O::lo(g0, g1);
     if constexpr (K == 2) {
-        return O::hi3(mh, ml, O::hi3(nh, nl, O::lo(x1, y1)));
+        // max(l0, l1, k0, k1, min(x1, y1), v, z)
+        return O::hi3(O::hi3(l0, l1, k0), O::hi3(k1, v, z), O::lo(x1, y1));
     } else if constexpr (K == 3) {
-        u16x2 mid = O::lo3(O::hi3(mh, ml, O::hi(nh, nl)), x1, y1);
-        return O::hi3(O::lo(mh, ml), O::lo(nh, nl), mid);
+        // median(p, q, r) with p = min(x1, y1), r = max(v, z) (the middle two
+        // of the pair maxima, either order) and q the largest pair minimum,
+        // as max(min(p, max(q, r)), min(q, r)); max(q, r) = max(q, v, z)
+        const u16x2 q = O::hi3(l0, l1, O::hi(k0, k1));
+        const u16x2 r = O::hi(v, z);
+        return O::hi(O::lo3(x1, y1, O::hi3(q, v, z)), O::lo(q, r));
     } else {
         static_assert(K == 4, "k = 2, 3, 4");
-        u16x2 b2 = O::lo(O::hi(mh, ml), O::hi(nh, nl));
-        u16x2 c13 = O::lo3(O::hi(O::lo(mh, ml), O::lo(nh, nl)), x1, y1);
-        return O::hi3(O::lo(l0, l1), O::lo(k0, k1), O::hi(b2, c13));
+        // max(min(a1, o3), a2, o4): a1 >= a2 the two largest pair minima, o3
+        // and o4 the third and fourth largest pair maxima
+        const u16x2 ma = O::hi(l0, l1), na = O::lo(l0, l1);
+        const u16x2 mb = O::hi(k0, k1), nb = O::lo(k0, k1);
+        const u16x2 a1 = O::hi(ma, mb);
+        const u16x2 o3 = O::lo3(x1, y1, O::hi(v, z)), o4 = O::lo(v, z);
+        // a2 = max(na, nb, min(ma, mb))
+        return O::hi3(O::hi3(O::lo(a1, o3), na, nb), O::lo(ma, mb), o4);
     }
 }
 
