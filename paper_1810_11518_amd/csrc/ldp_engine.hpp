@@ -302,9 +302,15 @@ __device__ __forceinline__ void step(const ImgView &im, uint32_t *lds_bins, Walk
     }
 }
 
-// The row walk of a task from its first code row: n rows.
+// The row walk of a task from its first code row: n >= 1 rows, as a loop of
+// three steps and a tail of one to `tail` steps (2 or 3, the same in every
+// lane of the wave).  A wave runs the loop as long as any of its lanes does
+// and the tail steps any lane needs, so it takes max(n) steps over its lanes
+// when they all run the loop equally often: n / 3 times with a tail of up to
+// 2, (n - 1) / 3 times with a tail of up to 3.
 template <int K, int MODE, bool HIST, bool CODES, bool ALIGNED>
-__device__ __forceinline__ void walk_rows(const ImgView &im, uint32_t *lds_bins, Walk &w, int32_t n)
+__device__ __forceinline__ void walk_rows(const ImgView &im, uint32_t *lds_bins, Walk &w, int32_t n,
+                                          int32_t tail)
 {
     RawRow raw;
     Row A, B, C;
@@ -317,7 +323,7 @@ __device__ __forceinline__ void walk_rows(const ImgView &im, uint32_t *lds_bins,
     load_raw<ALIGNED>(raw, im.rsrc, w.off);
     // the three rows rotate through A, B, C so no registers are copied
     // between rows
-    for (; n >= 3; n -= 3) {
+    for (; n > tail; n -= 3) {
         step<K, MODE, HIST, CODES, ALIGNED>(im, lds_bins, w, raw, A, B, C);
         step<K, MODE, HIST, CODES, ALIGNED>(im, lds_bins, w, raw, B, C, A);
         step<K, MODE, HIST, CODES, ALIGNED>(im, lds_bins, w, raw, C, A, B);
@@ -326,6 +332,8 @@ __device__ __forceinline__ void walk_rows(const ImgView &im, uint32_t *lds_bins,
         step<K, MODE, HIST, CODES, ALIGNED>(im, lds_bins, w, raw, A, B, C);
     if (n >= 2)
         step<K, MODE, HIST, CODES, ALIGNED>(im, lds_bins, w, raw, B, C, A);
+    if (n >= 3)
+        step<K, MODE, HIST, CODES, ALIGNED>(im, lds_bins, w, raw, C, A, B);
 }
 
 // Run code rows [r0, r1) of the column group `c`; with HIST they all lie in
@@ -343,12 +351,18 @@ __device__ __forceinline__ void run_task(const ImgView &im, uint32_t *lds_bins, 
     w.d0 = c.d0 + row_cells;
     w.d1 = c.d1 + row_cells;
     w.uniform_cell = c.uniform_cell;
+    // tail of 3 when the wave's lanes agree on (n - 1) / 3 (row bands of
+    // lengths 3j+1..3j+3, e.g. 17 and 18), else of 2 (lengths 3j..3j+2).
+    // (n - 1) / 3 as a multiply and shift, exact for n - 1 < 2^16.
+    const int32_t n = r1 - r0;
+    const uint32_t q = ((uint32_t)(n - 1) * 0xAAABu) >> 17;
+    const int32_t tail = __all(q == (uint32_t)__builtin_amdgcn_readfirstlane(q)) ? 3 : 2;
     // every row of every lane of the wave starts 4-aligned: the walk without
     // realignment (typical: all column groups but an image's last one)
     if (__all(((w.off | im.stride) & 3u) == 0))
-        walk_rows<K, MODE, HIST, CODES, true>(im, lds_bins, w, r1 - r0);
+        walk_rows<K, MODE, HIST, CODES, true>(im, lds_bins, w, n, tail);
     else
-        walk_rows<K, MODE, HIST, CODES, false>(im, lds_bins, w, r1 - r0);
+        walk_rows<K, MODE, HIST, CODES, false>(im, lds_bins, w, n, tail);
 }
 
 // Code rows [r0, r1) of a code map narrower than 8 columns: one lane, the
