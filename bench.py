@@ -38,15 +38,15 @@ VALU_SINGLE_ISSUE_T = 256 * 4 * 16 * 2.4e9 / 1e12
 # histogram paths counted; the loop with the fewest instructions, which waves
 # whose rows start 4-aligned run).  tests/test_isa_counts.py recompiles the
 # kernel and checks these figures against the generated code.
-VALU_PER_ROW_STEP = {1: 413 / 3, 2: 569 / 3, 3: 605 / 3, 4: 665 / 3, 5: 665 / 3, 6: 605 / 3,
-                     7: 569 / 3, 8: 45 / 3}
+VALU_PER_ROW_STEP = {1: 413 / 3, 2: 557 / 3, 3: 593 / 3, 4: 653 / 3, 5: 653 / 3, 6: 593 / 3,
+                     7: 557 / 3, 8: 45 / 3}
 # the same for ranking by response magnitude (flags LDP_RANK_MAGNITUDE), for
 # responses computed mask by mask (LDP_DIRECT_MASKS) and for LBP labels
 # (LDP_CODE_LBP, one kernel for every k)
-VALU_PER_ROW_STEP_MAGNITUDE = {1: 767 / 3, 2: 923 / 3, 3: 959 / 3, 4: 1019 / 3, 5: 1019 / 3,
-                               6: 959 / 3, 7: 923 / 3, 8: 45 / 3}
-VALU_PER_ROW_STEP_DIRECT = {1: 1043 / 3, 2: 1199 / 3, 3: 1235 / 3, 4: 1295 / 3, 5: 1295 / 3,
-                            6: 1235 / 3, 7: 1199 / 3, 8: 45 / 3}
+VALU_PER_ROW_STEP_MAGNITUDE = {1: 767 / 3, 2: 911 / 3, 3: 947 / 3, 4: 1007 / 3, 5: 1007 / 3,
+                               6: 947 / 3, 7: 911 / 3, 8: 45 / 3}
+VALU_PER_ROW_STEP_DIRECT = {1: 1043 / 3, 2: 1187 / 3, 3: 1223 / 3, 4: 1283 / 3, 5: 1283 / 3,
+                            6: 1223 / 3, 7: 1187 / 3, 8: 45 / 3}
 VALU_PER_ROW_STEP_LBP = 287 / 3
 # untimed work before the warm-up steps, so that timing starts at steady clocks
 DEVICE_WARMUP_S = 0.3
