@@ -72,6 +72,15 @@ __device__ __forceinline__ uint32_t udiv_small(uint32_t x, uint32_t d)
     return q + (x - __umul24(q, d) >= d ? 1u : 0u);
 }
 
+// floor(x / d) for any x and 1 <= d < 2^20: udiv_small when x < 2^20 (the
+// usual case), the full 32-bit division otherwise
+__device__ __forceinline__ uint32_t udiv_u32(uint32_t x, uint32_t d)
+{
+    if (x < (1u << 20))
+        return udiv_small(x, d);
+    return x / d;
+}
+
 // Histogram cells of a code map: code row r lies in cell row r*ay/by, code
 // column j in cell column j*ax/bx; ny x nx cells.
 //   cells (Eqs. 4-5 over a grid): ay = cells_y, by = Hc, ax = cells_x, bx = Wc;
@@ -200,13 +209,15 @@ __device__ __forceinline__ Cols group_cols(const Geom &geo, int32_t g, int32_t c
         // the 8 columns meet at most one cell boundary, so two divisions (the
         // first column's cell and the next cell's first column) place them
         // all.  Narrower cells: one division per column.
+        // (all products below 2^32: columns and cell counts are below 2^16)
         const bool wide = geo.bx >= 8u * geo.ax;
-        const uint32_t cxa = ((uint32_t)c.j0 * geo.ax) / geo.bx;
-        const uint32_t next = wide ? (uint32_t)geom_col_start(geo, (int32_t)cxa + 1, Wc) : 0u;
+        const uint32_t cxa = udiv_u32((uint32_t)c.j0 * geo.ax, geo.bx);
+        const uint32_t next =
+            wide ? min(udiv_u32((cxa + 1u) * geo.bx + geo.ax - 1u, geo.ax), (uint32_t)Wc) : 0u;
 #pragma unroll
         for (int p = 0; p < 8; ++p) {
             const uint32_t j = (uint32_t)(c.j0 + p);
-            const uint32_t cx = wide ? cxa + (j >= next ? 1u : 0u) : (j * geo.ax) / geo.bx;
+            const uint32_t cx = wide ? cxa + (j >= next ? 1u : 0u) : udiv_u32(j * geo.ax, geo.bx);
             const uint32_t d = (p < skip ? (uint32_t)ncell : cx - (uint32_t)cx0)
                                << (8 * ((p & 1) | ((p >> 1) & 2)));
             if (p & 2)
@@ -345,7 +356,7 @@ __device__ __forceinline__ void run_task(const ImgView &im, uint32_t *lds_bins, 
     Walk w;
     w.off = im.off0 + (uint32_t)r0 * im.stride + (uint32_t)c.j0;
     w.last_off = im.off0 + (uint32_t)(im.H - 1) * im.stride + (uint32_t)c.j0;
-    w.coff = (uint32_t)r0 * (uint32_t)im.Wc + (uint32_t)c.j0;
+    w.coff = __umul24((uint32_t)r0, (uint32_t)im.Wc) + (uint32_t)c.j0;  // both below 2^16
     // the cell row's first LDS cell, added to every pixel's byte
     const uint32_t row_cells = (rowb >> 10) * 0x01010101u;
     w.d0 = c.d0 + row_cells;
@@ -478,11 +489,11 @@ __device__ __forceinline__ void fused_item(const ImgView &im, uint32_t *lds, con
                 if (tid < base) {
                     const uint32_t m = (uint32_t)(ngroups - nx);
                     sb = udiv_small((uint32_t)tid, m);
-                    g = (uint32_t)tid - sb * m;
+                    g = (uint32_t)tid - __umul24(sb, m);
                     nb = (uint32_t)nsub;
                 } else {
                     sb = udiv_small((uint32_t)(tid - base), (uint32_t)nx);
-                    g = (uint32_t)(ngroups - nx) + (uint32_t)(tid - base) - sb * (uint32_t)nx;
+                    g = (uint32_t)(ngroups - nx) + (uint32_t)(tid - base) - __umul24(sb, (uint32_t)nx);
                     nb = (uint32_t)nsub + 1;
                 }
                 const Cols c = group_cols<true>(geo, (int32_t)g, c_lo, c_hi, cx0, ncell, im.Wc);
@@ -493,11 +504,13 @@ __device__ __forceinline__ void fused_item(const ImgView &im, uint32_t *lds, con
                     }
                     // band sb of nb over nr rows: [nr*sb/nb, nr*(sb+1)/nb).  With
                     // nr = qn*nb + rn, nr*s/nb = qn*s + rn*s/nb, and rn*s < nb^2
-                    // <= 2^20 (nb <= 1024 threads)
+                    // <= 2^20 (nb <= 1024 threads); every product has factors
+                    // below 2^24 and a result below 2^32 (24-bit multiplies)
                     const uint32_t nr = (uint32_t)max(b - a, 0);
-                    const uint32_t qn = udiv_small(nr, nb), rn = nr - qn * nb;
-                    const int32_t a0 = a + (int32_t)(qn * sb + udiv_small(rn * sb, nb));
-                    const int32_t a1 = a + (int32_t)(qn * (sb + 1) + udiv_small(rn * (sb + 1), nb));
+                    const uint32_t qn = udiv_small(nr, nb), rn = nr - __umul24(qn, nb);
+                    const uint32_t rs = __umul24(rn, sb), qs = __umul24(qn, sb);
+                    const int32_t a0 = a + (int32_t)(qs + udiv_small(rs, nb));
+                    const int32_t a1 = a + (int32_t)(qs + qn + udiv_small(rs + rn, nb));
                     if (a1 > a0)
                         run_task<K, MODE, true, CODES>(im, lds, (cy - cy0) * row_bytes, c, a0, a1);
                 }
