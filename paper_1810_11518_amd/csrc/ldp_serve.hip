@@ -10,11 +10,22 @@
 // soon as memory and slots free up and run concurrently with them.  When a
 // batch's completion event has fired its requests are reported done and their
 // memory and slots are released.
+//
+// Pageable buffers go through a page-locked host mirror of the pool (same
+// offsets and admission): the dispatcher packs a request's image into its
+// mirror region, the kernel reads it there over the bus as it reads a
+// page-locked caller's image and writes its codes and histograms there, and
+// they are copied to the caller's buffers once the batch has finished.  No
+// copy is enqueued: a copy from or to pageable memory would hold the
+// dispatcher until it completes (results: until the batch has run), and every
+// enqueued copy costs the dispatcher microseconds of runtime work.  The device
+// pool serves pageable requests only when the mirror cannot be allocated.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
+#include <cstring>
 #include <deque>
 #include <map>
 #include <mutex>
@@ -102,6 +113,7 @@ struct Batch {
     int slot = -1;
     double t_launch = 0;
     int status = LDP_OK;
+    bool staged = false;  // results are in the pool's page-locked mirror
 };
 
 }  // namespace
@@ -110,6 +122,12 @@ struct ldp_server {
     ldp_server_config cfg{};
     int64_t hist_bytes = 0;
     uint8_t *d_pool = nullptr;
+    // page-locked mirror of d_pool for pageable requests (allocated at
+    // creation for pools up to kEagerMirror bytes, else at first need; null if
+    // that fails: such requests then copy from and to pageable memory directly)
+    uint8_t *h_mirror = nullptr;
+    uint8_t *d_mirror = nullptr;  // its address for the kernel
+    bool mirror_tried = false;
     Pool *pool = nullptr;
     std::vector<hipStream_t> streams;
     std::vector<hipEvent_t> events;
@@ -138,12 +156,82 @@ namespace {
 // item, row bands of >= 4 rows, large workgroups) rather than few long ones.
 const ldp_tune kServeTune = {LDP_SERVE_THREADS, 0, 1, 0, {{INT64_MAX, 1, 4}}};
 
+// Pools up to this size get their page-locked mirror at server creation.
+constexpr int64_t kEagerMirror = int64_t(256) << 20;
+
+uint8_t *mirror(ldp_server *s)
+{
+    if (!s->h_mirror && !s->mirror_tried) {
+        s->mirror_tried = true;
+        void *d = nullptr;
+        if (hipHostMalloc(&s->h_mirror, (size_t)s->cfg.pool_bytes) != hipSuccess) {
+            s->h_mirror = nullptr;
+            (void)hipGetLastError();
+        } else if (hipHostGetDevicePointer(&d, s->h_mirror, 0) != hipSuccess || !d) {
+            (void)hipGetLastError();
+            (void)hipHostFree(s->h_mirror);
+            s->h_mirror = nullptr;
+        } else {
+            s->d_mirror = static_cast<uint8_t *>(d);
+        }
+    }
+    return s->h_mirror;
+}
+
+// Results of a finished batch from the pool's mirror to the callers' buffers.
+void copy_out(ldp_server *s, const Batch &b)
+{
+    for (const Req *r : b.reqs) {
+        const uint8_t *m = s->h_mirror + r->off + r->img_bytes;
+        if (r->codes)
+            std::memcpy(r->codes, m, (size_t)(r->H - 2) * (r->W - 2));
+        if (!r->hist_dev)
+            std::memcpy(r->hist, m + r->code_bytes, (size_t)s->hist_bytes);
+    }
+}
+
 // Device work of one batch on its stream; returns a status.
 int launch_batch(ldp_server *s, Batch &b)
 {
     if (s->cfg.dry_run)
         return LDP_OK;
     hipStream_t st = s->streams[b.slot];
+    bool copies = false;
+    for (Req *r : b.reqs)
+        copies = copies || r->bytes > 0;
+    uint8_t *hm = copies ? mirror(s) : nullptr;
+    b.staged = hm != nullptr;
+    if (hm) {
+        // The batch's pageable images packed into the mirror, which the
+        // kernel then reads in place like a page-locked caller's image (and
+        // writes codes and histograms to): no copy is enqueued at all.
+        std::vector<ldp_image_desc> descs;
+        descs.reserve(b.reqs.size());
+        for (const Req *r : b.reqs) {
+            uint8_t *m = hm + r->off, *dm = s->d_mirror + r->off;
+            const uint8_t *img = r->img_dev;
+            int64_t pitch = r->stride;
+            if (!img) {
+                if (r->stride == r->W)
+                    std::memcpy(m, r->img, (size_t)r->H * r->W);
+                else
+                    for (int32_t y = 0; y < r->H; ++y)
+                        std::memcpy(m + (size_t)y * r->W, r->img + (size_t)y * r->stride,
+                                    (size_t)r->W);
+                img = dm;
+                pitch = r->W;
+            }
+            uint8_t *codes = r->codes ? dm + r->img_bytes : nullptr;
+            uint32_t *hist = r->hist_dev ? r->hist_dev
+                                         : reinterpret_cast<uint32_t *>(dm + r->img_bytes +
+                                                                        r->code_bytes);
+            descs.push_back({img, codes, hist, pitch, r->H, r->W});
+        }
+        const int rc = ldp::run_batch(s->plans[b.slot], descs.data(), (int32_t)descs.size(), st);
+        if (rc != LDP_OK)
+            return rc;
+        return hipEventRecord(s->events[b.slot], st) == hipSuccess ? LDP_OK : LDP_ERR_HIP;
+    }
     std::vector<ldp_image_desc> descs;
     descs.reserve(b.reqs.size());
     for (Req *r : b.reqs) {
@@ -203,25 +291,43 @@ void dispatcher(ldp_server *s)
     std::unique_lock<std::mutex> lk(s->mu);
     for (;;) {
         bool progressed = false;
-        // retire finished batches: report, then free memory and slots
-        const double t = now_s();
+        // retire finished batches: copy staged results out (without the lock:
+        // only this thread touches batches in flight, their pool regions and
+        // slots), report, then free memory and slots
+        double t = now_s();
+        std::vector<Batch> fin;
         for (size_t i = 0; i < s->inflight.size();) {
-            Batch &b = s->inflight[i];
-            if (!batch_finished(s, b, t)) {
+            if (!batch_finished(s, s->inflight[i], t)) {
                 ++i;
                 continue;
             }
-            for (Req *r : b.reqs) {
-                if (r->bytes)
-                    s->pool->release(r->off, r->bytes);
-                s->done.push_back({r->id, r->t_submit, r->t_admit, t, b.status,
-                                   (int32_t)b.reqs.size()});
-                delete r;
-            }
-            s->inflight_reqs -= (int)b.reqs.size();
-            s->st.completed += (int64_t)b.reqs.size();
-            s->slot_busy[b.slot] = 0;
+            fin.push_back(std::move(s->inflight[i]));
             s->inflight.erase(s->inflight.begin() + (long)i);
+        }
+        if (!fin.empty()) {
+            bool staged = false;
+            for (const Batch &b : fin)
+                staged = staged || (b.staged && b.status == LDP_OK);
+            if (staged) {
+                lk.unlock();
+                for (const Batch &b : fin)
+                    if (b.staged && b.status == LDP_OK)
+                        copy_out(s, b);
+                t = now_s();
+                lk.lock();
+            }
+            for (Batch &b : fin) {
+                for (Req *r : b.reqs) {
+                    if (r->bytes)
+                        s->pool->release(r->off, r->bytes);
+                    s->done.push_back({r->id, r->t_submit, r->t_admit, t, b.status,
+                                       (int32_t)b.reqs.size()});
+                    delete r;
+                }
+                s->inflight_reqs -= (int)b.reqs.size();
+                s->st.completed += (int64_t)b.reqs.size();
+                s->slot_busy[b.slot] = 0;
+            }
             progressed = true;
         }
         if (progressed)
@@ -304,6 +410,8 @@ void release_server(ldp_server *s)
             (void)hipStreamDestroy(st);
     if (s->d_pool)
         (void)hipFree(s->d_pool);
+    if (s->h_mirror)
+        (void)hipHostFree(s->h_mirror);
     delete s->pool;
     for (Req *r : s->pending)
         delete r;
@@ -342,6 +450,8 @@ int ldp_server_create(ldp_server **out, const ldp_server_config *cfg)
             release_server(s);
             return LDP_ERR_NO_MEMORY;
         }
+        if (c.pool_bytes <= kEagerMirror)
+            (void)mirror(s);
         for (int i = 0; i < c.depth; ++i) {
             hipStream_t st = nullptr;
             hipEvent_t ev = nullptr;

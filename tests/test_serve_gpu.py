@@ -125,14 +125,18 @@ def test_histograms_only_requests(lib):
         assert (hist.reshape(7, 6, 256) == oracle_c.ldp_extract(img, 3, 7, 6)[1]).all()
 
 
-def test_pageable_buffers_take_the_copy_path(lib):
+@pytest.mark.parametrize("pool", [1 << 28, 3 << 28])
+def test_pageable_buffers_take_the_copy_path(lib, pool):
     """Plain (pageable) host buffers: the server copies images in and results
-    out (pinned images and histograms are read and written by the kernel in
-    place, here also pinned images with padded rows); same results."""
+    out through a page-locked mirror of its pool (made at creation for pools
+    up to 256 MiB, at the first such request above), pageable images with
+    padded rows packed on the way; pinned images and histograms are read and
+    written by the kernel in place, here also pinned images with padded rows;
+    same results."""
     r = np.random.default_rng(17)
-    srv = lib.Server(1 << 28, max_inflight=64, max_batch=16, depth=2, k=3, cells_y=7, cells_x=6)
+    srv = lib.Server(pool, max_inflight=64, max_batch=16, depth=2, k=3, cells_y=7, cells_x=6)
     keep = []
-    for j in range(12):
+    for j in range(16):
         H, W = int(r.integers(12, 400)), int(r.integers(12, 500))
         img = synth.image(synth.KIND_BLUR_RECTS, 19, j, H, W)
         if j % 3 == 2:
@@ -140,6 +144,10 @@ def test_pageable_buffers_take_the_copy_path(lib):
             padded[:, :W] = img
             img = padded[:, :W]
             keep.append(kp)
+        elif j % 4 == 1:
+            padded = np.zeros((H, W + 7), np.uint8)       # pageable, pitch W + 7
+            padded[:, :W] = img
+            img = padded[:, :W]
         codes = np.full((H - 2) * (W - 2), 0xAB, np.uint8)
         hist = np.full(7 * 6 * 256, 7, np.uint32)
         if j % 2:
@@ -148,7 +156,7 @@ def test_pageable_buffers_take_the_copy_path(lib):
             keep.append(kh)
         srv.submit(img, hist, codes)
         keep.append((img, codes, hist))
-    _drain(srv, 12)
+    _drain(srv, 16)
     srv.close()
     for img, codes, hist in [x for x in keep if isinstance(x, tuple)]:
         want_c, want_h = oracle_c.ldp_extract(img, 3, 7, 6)
