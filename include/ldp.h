@@ -316,21 +316,30 @@ int ldp_batch_plan_destroy(ldp_batch_plan *plan);
 /* ---------------------------------------------------------------- serving
  *
  * Continuous batching of single-image requests.  A request (a HOST image and
- * HOST result buffers) is admitted when the server's device memory pool has
- * room for its image, codes and histograms and a request slot is free;
- * otherwise it waits, in arrival order.  A dispatcher thread copies admitted
- * images to the device and launches them as one persistent batch
+ * HOST result buffers) is admitted when the server's memory pool has room for
+ * its image, codes and histograms (the buffers the GPU cannot address in
+ * place) and a request slot is free; otherwise it waits, in arrival order.
+ * The pool has a page-locked host mirror of the same size (made at creation
+ * for pools up to 256 MiB, at the first request that needs it above): a
+ * dispatcher thread packs each admitted pageable image into the request's
+ * mirror region and launches the admitted requests as one persistent batch
  * (ldp_batch_launch: a small batch's tables travel in the launch arguments,
  * a larger one's are uploaded; the work queue lives on the device) on one
- * of `depth` streams, so requests that arrive while earlier batches run are
- * admitted as memory frees up and their work overlaps on the device.  When a
- * batch's results are back on the host its memory and slots are released.
- * Results are exactly those of ldp_extract on the image alone.
+ * of `depth` streams; the kernel reads the images there and writes codes
+ * and histograms there, over the bus, and the dispatcher copies them to the
+ * caller's buffers once the batch has finished.  Requests that arrive while
+ * earlier batches run are admitted as memory frees up and their work
+ * overlaps on the device.  When a batch's results are on the host its
+ * memory and slots are released.  Without the mirror (its allocation
+ * failed) the device pool holds the requests and images and results are
+ * copied in and out on the batch's stream.  Results are exactly those of
+ * ldp_extract on the image alone.
  */
 typedef struct ldp_server ldp_server;
 
 typedef struct ldp_server_config {
-    int64_t pool_bytes;    /* device pool for images + codes + histograms */
+    int64_t pool_bytes;    /* pool for images + codes + histograms (device
+                            * memory and a page-locked host mirror of it) */
     int32_t max_inflight;  /* requests admitted at once (slots) */
     int32_t max_batch;     /* requests per launch */
     int32_t depth;         /* launches in flight at once (streams), 1..8 */
@@ -348,7 +357,7 @@ typedef struct ldp_completion {
     int64_t id;
     double t_submit;  /* when ldp_server_submit accepted it */
     double t_admit;   /* when it got device memory and a slot */
-    double t_done;    /* when the dispatcher saw its results on the host */
+    double t_done;    /* when its results were in the caller's buffers */
     int32_t status;   /* LDP_OK or the error of its batch */
     int32_t batch_size;
 } ldp_completion;
@@ -367,8 +376,8 @@ typedef struct ldp_server_stats {
 /* Monotonic clock (seconds) used for every server timestamp. */
 double ldp_now(void);
 
-/* Create a server (allocates the pool, streams and batch plans; starts the
- * dispatcher thread).  Without dry_run it also launches every slot's batch
+/* Create a server (allocates the pool and, up to 256 MiB, its page-locked
+ * mirror, streams and batch plans; starts the dispatcher thread).  Without dry_run it also launches every slot's batch
  * kernels (graph and argument-table forms) once on an empty batch and runs
  * one small copy of each kind on the slot's stream, synchronously, so that
  * one-time runtime set-up does not fall on the first requests (a few
@@ -379,10 +388,10 @@ int ldp_server_create(ldp_server **server, const ldp_server_config *config);
 /* Queue one request.  img is HOST memory, H x W with pitch `stride`; codes
  * ((H-2)*(W-2) bytes, may be NULL) and hist (cells_y*cells_x*256 uint32) are
  * HOST outputs written before the request completes.  All three buffers must
- * stay valid until completion; page-locked memory gives asynchronous copies,
- * and page-locked img and hist buffers that the GPU addresses at their host
- * addresses are read and written by the kernel in place (no copy in, no
- * device copy of the histograms, no copy back).  Returns the
+ * stay valid until completion; page-locked img and hist buffers that the GPU
+ * addresses at their host addresses are read and written by the kernel in
+ * place (no pool space, no host copy), other buffers go through the pool's
+ * mirror (one host copy each way).  Returns the
  * request id in *id.  Errors: LDP_ERR_INVALID_ARG (bad sizes),
  * LDP_ERR_NO_MEMORY (the request can never fit the pool: rejected). */
 int ldp_server_submit(ldp_server *server, const uint8_t *img, int32_t H, int32_t W,
