@@ -350,7 +350,14 @@ typedef struct ldp_server_config {
                             * dry_run_us microseconds after launch, outputs are
                             * not written */
     int32_t dry_run_us;
+    int32_t flags;         /* 0, or LDP_SERVER_NO_MIRROR: no page-locked mirror;
+                            * buffers the GPU cannot address in place go
+                            * through the device pool with copies in and out
+                            * (the path taken when the mirror cannot be
+                            * allocated) */
 } ldp_server_config;
+
+#define LDP_SERVER_NO_MIRROR 1
 
 /* Completion record of a request; times are ldp_now() seconds. */
 typedef struct ldp_completion {

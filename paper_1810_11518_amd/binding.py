@@ -84,7 +84,11 @@ class ServerConfig(ctypes.Structure):
     _fields_ = [("pool_bytes", ctypes.c_int64), ("max_inflight", ctypes.c_int32),
                 ("max_batch", ctypes.c_int32), ("depth", ctypes.c_int32), ("k", ctypes.c_int32),
                 ("cells_y", ctypes.c_int32), ("cells_x", ctypes.c_int32),
-                ("dry_run", ctypes.c_int32), ("dry_run_us", ctypes.c_int32)]
+                ("dry_run", ctypes.c_int32), ("dry_run_us", ctypes.c_int32),
+                ("flags", ctypes.c_int32)]
+
+
+LDP_SERVER_NO_MIRROR = 1
 
 
 class Completion(ctypes.Structure):
@@ -406,11 +410,12 @@ class Server:
     """
 
     def __init__(self, pool_bytes, max_inflight, max_batch, depth, k, cells_y, cells_x,
-                 dry_run=False, dry_run_us=0):
+                 dry_run=False, dry_run_us=0, no_mirror=False):
         self._lib = load()
         self._srv = ctypes.c_void_p()
         cfg = ServerConfig(int(pool_bytes), int(max_inflight), int(max_batch), int(depth), int(k),
-                           int(cells_y), int(cells_x), 1 if dry_run else 0, int(dry_run_us))
+                           int(cells_y), int(cells_x), 1 if dry_run else 0, int(dry_run_us),
+                           LDP_SERVER_NO_MIRROR if no_mirror else 0)
         _check(self._lib.ldp_server_create(ctypes.byref(self._srv), ctypes.byref(cfg)),
                "ldp_server_create")
         self.cells = (cells_y, cells_x)

@@ -161,6 +161,8 @@ constexpr int64_t kEagerMirror = int64_t(256) << 20;
 
 uint8_t *mirror(ldp_server *s)
 {
+    if (s->cfg.flags & LDP_SERVER_NO_MIRROR)
+        return nullptr;
     if (!s->h_mirror && !s->mirror_tried) {
         s->mirror_tried = true;
         void *d = nullptr;
@@ -432,7 +434,8 @@ int ldp_server_create(ldp_server **out, const ldp_server_config *cfg)
     const ldp_server_config c = *cfg;
     if (c.pool_bytes < 4096 || c.max_inflight < 1 || c.max_batch < 1 || c.depth < 1 ||
         c.depth > 8 || c.k < 1 || c.k > 8 || c.cells_y < 1 || c.cells_x < 1 ||
-        c.cells_y > LDP_MAX_SIDE - 2 || c.cells_x > LDP_MAX_SIDE - 2 || c.dry_run_us < 0)
+        c.cells_y > LDP_MAX_SIDE - 2 || c.cells_x > LDP_MAX_SIDE - 2 || c.dry_run_us < 0 ||
+        (c.flags & ~LDP_SERVER_NO_MIRROR) != 0)
         return LDP_ERR_INVALID_ARG;
     ldp_server *s = new (std::nothrow) ldp_server();
     if (!s)

@@ -114,6 +114,11 @@ def test_invalid_arguments_return_before_any_launch(lib):
     assert lib.ldp_server_create(ctypes.byref(srv), ctypes.byref(bad)) == E
     bad = binding.ServerConfig(1 << 20, 1, 1, 9, 3, 7, 6, 1, 0)
     assert lib.ldp_server_create(ctypes.byref(srv), ctypes.byref(bad)) == E
+    bad = binding.ServerConfig(1 << 20, 1, 1, 1, 3, 7, 6, 1, 0, 2)   # unknown flag
+    assert lib.ldp_server_create(ctypes.byref(srv), ctypes.byref(bad)) == E
+    ok = binding.ServerConfig(1 << 20, 1, 1, 1, 3, 7, 6, 1, 0, binding.LDP_SERVER_NO_MIRROR)
+    assert lib.ldp_server_create(ctypes.byref(srv), ctypes.byref(ok)) == binding.LDP_OK
+    assert lib.ldp_server_destroy(srv) == binding.LDP_OK
 
 
 def test_compact_bin_counts(lib):

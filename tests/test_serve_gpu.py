@@ -125,16 +125,18 @@ def test_histograms_only_requests(lib):
         assert (hist.reshape(7, 6, 256) == oracle_c.ldp_extract(img, 3, 7, 6)[1]).all()
 
 
-@pytest.mark.parametrize("pool", [1 << 28, 3 << 28])
-def test_pageable_buffers_take_the_copy_path(lib, pool):
+@pytest.mark.parametrize("pool, no_mirror", [(1 << 28, False), (3 << 28, False), (1 << 28, True)])
+def test_pageable_buffers_take_the_copy_path(lib, pool, no_mirror):
     """Plain (pageable) host buffers: the server copies images in and results
     out through a page-locked mirror of its pool (made at creation for pools
     up to 256 MiB, at the first such request above), pageable images with
-    padded rows packed on the way; pinned images and histograms are read and
-    written by the kernel in place, here also pinned images with padded rows;
-    same results."""
+    padded rows packed on the way -- or, without the mirror, through the
+    device pool with copies in and out; pinned images and histograms are read
+    and written by the kernel in place, here also pinned images with padded
+    rows; same results."""
     r = np.random.default_rng(17)
-    srv = lib.Server(pool, max_inflight=64, max_batch=16, depth=2, k=3, cells_y=7, cells_x=6)
+    srv = lib.Server(pool, max_inflight=64, max_batch=16, depth=2, k=3, cells_y=7, cells_x=6,
+                     no_mirror=no_mirror)
     keep = []
     for j in range(16):
         H, W = int(r.integers(12, 400)), int(r.integers(12, 500))
