@@ -482,8 +482,10 @@ def serve_bench(binding, synth, torch, rates, n_req, k=3, cells=(7, 6), pool_ima
                 addresses: the kernel reads the image and writes the
                 histograms over PCIe, no pool space;
       copy      pageable images and histogram buffers: every request is
-                admitted into a 32 MiB device pool (image + histograms),
-                copied in and out, so admission waits for pool memory under
+                admitted into a 32 MiB pool (image + histograms) whose
+                page-locked host mirror the server packs the image into and
+                the kernel reads and writes in place; results are copied out
+                after the batch; admission waits for pool memory under
                 load."""
     _, Hs, Ws = synth.serve_stream(1000, pool_images)
     off, strides, total = synth.layout(Hs, Ws)
@@ -616,7 +618,9 @@ def main():
                              "[64,2048], k=3, 7x6 cells, histogram outputs; latency from "
                              "scheduled arrival to results on the host, after 0.25 s of "
                              "untimed load at the same rate; admission delay = admitted - "
-                             "submitted",
+                             "submitted; in_place: page-locked buffers the kernel reads and "
+                             "writes; copy: pageable buffers through the page-locked mirror "
+                             "of a 32 MiB pool",
                  "paths": serve_bench(binding, synth, torch, rates, args.serve_requests)}
 
     # ---- variants on the same batch (they overwrite the outputs)
