@@ -3,7 +3,7 @@
 // A task is one column group (8 adjacent code columns) of one image over a
 // range of code rows that lies inside one cell row.  The lane keeps the three
 // image rows around the current code row in registers, loads each new row
-// once (prefetched one row ahead) with hardware bounds-checked buffer loads,
+// once (two rows ahead) with hardware bounds-checked buffer loads,
 // computes the 8 codes, stores them and counts them in the LDS histogram.
 //
 // Every lane owns 8 code columns: the last group of a row is moved left so
@@ -277,15 +277,21 @@ __device__ __forceinline__ void lds_count(uint32_t addr, uint32_t n)
                            __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// One code row: the next image row arrives in `raw` and becomes `b`; t and m
-// are the two rows above.
+// One code row: the next image row arrives in `raw` and becomes `b` (t and m
+// are the two rows above); the row after it moves from `raw2` to `raw`, and
+// the row after that is loaded into `raw2` (clamped to the image's last row).
+// Loading two rows ahead measured 1.2% faster on the batched kernel than one
+// row ahead, whose next step waited for the previous row's code store too,
+// and faster than giving each row slot its own buffer (no copies, but more
+// live registers: setup values spilled to scratch).
 template <int K, int MODE, bool HIST, bool CODES, bool ALIGNED>
 __device__ __forceinline__ void step(const ImgView &im, uint32_t *lds_bins, Walk &w, RawRow &raw,
-                                     const Row &t, const Row &m, Row &b)
+                                     const Row &t, const Row &m, Row &b, RawRow &raw2)
 {
     unpack_raw<MODE, ALIGNED>(b, raw);
+    raw = raw2;
     w.off = min(w.off + im.stride, w.last_off);
-    load_raw<ALIGNED>(raw, im.rsrc, w.off);  // prefetch the row after (clamped to the last)
+    load_raw<ALIGNED>(raw2, im.rsrc, w.off);
     uint32_t q0, q1;
     code_row<K, MODE>(t, m, b, q0, q1);
     if constexpr (CODES) {
@@ -331,20 +337,23 @@ __device__ __forceinline__ void walk_rows(const ImgView &im, uint32_t *lds_bins,
     load_raw<ALIGNED>(raw, im.rsrc, w.off);
     unpack_raw<MODE, ALIGNED>(B, raw);
     w.off += im.stride;
-    load_raw<ALIGNED>(raw, im.rsrc, w.off);
+    load_raw<ALIGNED>(raw, im.rsrc, w.off);  // rows r0 .. r0 + 2 are in the image
+    RawRow raw2;
+    w.off = min(w.off + im.stride, w.last_off);
+    load_raw<ALIGNED>(raw2, im.rsrc, w.off);
     // the three rows rotate through A, B, C so no registers are copied
     // between rows
     for (; n > tail; n -= 3) {
-        step<K, MODE, HIST, CODES, ALIGNED>(im, lds_bins, w, raw, A, B, C);
-        step<K, MODE, HIST, CODES, ALIGNED>(im, lds_bins, w, raw, B, C, A);
-        step<K, MODE, HIST, CODES, ALIGNED>(im, lds_bins, w, raw, C, A, B);
+        step<K, MODE, HIST, CODES, ALIGNED>(im, lds_bins, w, raw, A, B, C, raw2);
+        step<K, MODE, HIST, CODES, ALIGNED>(im, lds_bins, w, raw, B, C, A, raw2);
+        step<K, MODE, HIST, CODES, ALIGNED>(im, lds_bins, w, raw, C, A, B, raw2);
     }
     if (n >= 1)
-        step<K, MODE, HIST, CODES, ALIGNED>(im, lds_bins, w, raw, A, B, C);
+        step<K, MODE, HIST, CODES, ALIGNED>(im, lds_bins, w, raw, A, B, C, raw2);
     if (n >= 2)
-        step<K, MODE, HIST, CODES, ALIGNED>(im, lds_bins, w, raw, B, C, A);
+        step<K, MODE, HIST, CODES, ALIGNED>(im, lds_bins, w, raw, B, C, A, raw2);
     if (n >= 3)
-        step<K, MODE, HIST, CODES, ALIGNED>(im, lds_bins, w, raw, C, A, B);
+        step<K, MODE, HIST, CODES, ALIGNED>(im, lds_bins, w, raw, C, A, B, raw2);
 }
 
 // Run code rows [r0, r1) of the column group `c`; with HIST they all lie in
