@@ -337,14 +337,18 @@ def variant_bench(binding, torch, args, b, k, tune, ms_signed, sample, saved):
                                          [whist.data_ptr() + int(o) for o in hoff],
                                          [int(d.stride) for d in b.descs],
                                          [int(d.H) for d in b.descs], [int(d.W) for d in b.descs])
-        plan = binding.BatchPlan(b.n, b.pixels, k, w, w, tune, windows=True, max_width=max_w)
+        # the autotuner's window-plan choice for this window size, else the
+        # batch's own tune
+        wtune = autotune.lookup(b.Hs, b.Ws, k, (w, w), windows=True) or tune
+        plan = binding.BatchPlan(b.n, b.pixels, k, w, w, wtune, windows=True, max_width=max_w)
         plan.set(wdescs)
         items, _ = plan.info()
         ms = _timed(torch, plan.run, args.variant_steps)
         plan.close()
         wb = int((b.Hs.astype(np.int64) * b.Ws).sum() + b.code_pixels + nbins.sum() * 4)
         wins.append({"window": w, "windows_per_image": int(ny[0] * nx[0]),
-                     "windows": int((ny * nx).sum()), "work_items": items, "ms": round(ms, 4),
+                     "windows": int((ny * nx).sum()), "work_items": items, "tune": wtune,
+                     "ms": round(ms, 4),
                      "value": round(b.pixels / (ms * 1e-3) / 1e6, 1), "unit": "Mpixel/s",
                      "hbm": hbm(wb, ms)})
         del whist

@@ -46,11 +46,14 @@ def size_signature(Hs, Ws):
     return "mix:%d/%d/%d" % tuple(q)
 
 
-def key(Hs, Ws, k, cells, flags=0):
-    """Cache key: architecture, k, cell grid, size signature, and the
-    ldp_*_ex flags when set (the variants weigh arithmetic against memory
-    traffic differently, so their best split differs)."""
+def key(Hs, Ws, k, cells, flags=0, windows=False):
+    """Cache key: architecture, k, cell grid (or window size, with "|win"),
+    size signature, and the ldp_*_ex flags when set (the variants weigh
+    arithmetic against memory traffic differently, so their best split
+    differs)."""
     base = "%s|k%d|%dx%d|%s" % (arch(), k, cells[0], cells[1], size_signature(Hs, Ws))
+    if windows:
+        base += "|win"
     return base if not flags else base + "|f%d" % flags
 
 
@@ -61,9 +64,10 @@ def load_cache(path=CACHE):
     return {}
 
 
-def lookup(Hs, Ws, k, cells, path=CACHE, flags=0):
-    """Cached tune dict for this batch shape (and flags), or None."""
-    return load_cache(path).get(key(Hs, Ws, k, cells, flags), {}).get("tune")
+def lookup(Hs, Ws, k, cells, path=CACHE, flags=0, windows=False):
+    """Cached tune dict for this batch shape (and flags; window plans when
+    `windows`, with cells = the window size), or None."""
+    return load_cache(path).get(key(Hs, Ws, k, cells, flags, windows), {}).get("tune")
 
 
 def default_classes(Hs, Ws, cells_y):
@@ -78,10 +82,20 @@ def default_classes(Hs, Ws, cells_y):
             dict(cell_rows_per_item=1, rows_per_task=8)]
 
 
-def _time_plan(binding, descs, n, pixels, k, cells, tune, reps=8, rounds=3, flags=0):
+def _plan(binding, n, pixels, k, cells, tune, flags, max_width):
+    """A batch plan: over the cell grid, or over windows of cells[0] x cells[1]
+    code pixels when max_width (the widest image) is given."""
+    if max_width:
+        return binding.BatchPlan(n, pixels, k, cells[0], cells[1], tune, flags=flags,
+                                 windows=True, max_width=max_width)
+    return binding.BatchPlan(n, pixels, k, cells[0], cells[1], tune, flags=flags)
+
+
+def _time_plan(binding, descs, n, pixels, k, cells, tune, reps=8, rounds=3, flags=0,
+               max_width=0):
     """Best mean launch time (ms) over `rounds` rounds of `reps` launches."""
     import torch
-    plan = binding.BatchPlan(n, pixels, k, cells[0], cells[1], tune, flags=flags)
+    plan = _plan(binding, n, pixels, k, cells, tune, flags, max_width)
     try:
         plan.set(descs)
         for _ in range(2):
@@ -102,10 +116,10 @@ def _time_plan(binding, descs, n, pixels, k, cells, tune, reps=8, rounds=3, flag
         plan.close()
 
 
-def _warm_up(binding, descs, n, pixels, k, cells, tune, seconds=0.3, flags=0):
+def _warm_up(binding, descs, n, pixels, k, cells, tune, seconds=0.3, flags=0, max_width=0):
     """Keep the device busy with this batch for about `seconds`."""
     import torch
-    plan = binding.BatchPlan(n, pixels, k, cells[0], cells[1], tune, flags=flags)
+    plan = _plan(binding, n, pixels, k, cells, tune, flags, max_width)
     try:
         plan.set(descs)
         t_end = time.time() + seconds
@@ -117,17 +131,21 @@ def _warm_up(binding, descs, n, pixels, k, cells, tune, seconds=0.3, flags=0):
         plan.close()
 
 
-def tune_batch(descs, Hs, Ws, k, cells, budget_s=60.0, verbose=False, flags=0):
+def tune_batch(descs, Hs, Ws, k, cells, budget_s=60.0, verbose=False, flags=0, windows=False,
+               start=None):
     """Coordinate descent over ldp_tune for the device-resident batch `descs`
-    (a ctypes ImageDesc array) and ldp_*_ex `flags`.  Returns (best tune
+    (a ctypes ImageDesc array) and ldp_*_ex `flags`; with `windows`, for a
+    window plan of cells[0] x cells[1] code pixels.  `start` is the first
+    candidate (default: 256 threads, default classes).  Returns (best tune
     dict, best ms)."""
     from . import binding
     n = len(descs)
     pixels = int((np.asarray(Hs, dtype=np.int64) * np.asarray(Ws, dtype=np.int64)).sum())
+    mw = int(np.asarray(Ws).max()) if windows else 0
     t_end = time.time() + budget_s
-    best = dict(block_threads=256, classes=default_classes(Hs, Ws, cells[0]))
-    _warm_up(binding, descs, n, pixels, k, cells, best, flags=flags)
-    best_ms = _time_plan(binding, descs, n, pixels, k, cells, best, flags=flags)
+    best = start or dict(block_threads=256, classes=default_classes(Hs, Ws, cells[0]))
+    _warm_up(binding, descs, n, pixels, k, cells, best, flags=flags, max_width=mw)
+    best_ms = _time_plan(binding, descs, n, pixels, k, cells, best, flags=flags, max_width=mw)
     seen = {json.dumps(best, sort_keys=True): best_ms}
 
     def attempt(cand):
@@ -136,7 +154,7 @@ def tune_batch(descs, Hs, Ws, k, cells, budget_s=60.0, verbose=False, flags=0):
         if s in seen or time.time() > t_end:
             return
         try:
-            ms = _time_plan(binding, descs, n, pixels, k, cells, cand, flags=flags)
+            ms = _time_plan(binding, descs, n, pixels, k, cells, cand, flags=flags, max_width=mw)
         except binding.LdpError:
             return
         seen[s] = ms
@@ -164,7 +182,8 @@ def tune_batch(descs, Hs, Ws, k, cells, budget_s=60.0, verbose=False, flags=0):
     again = {s: float("inf") for s, _ in lead}
     for _ in range(3):
         for s in again:
-            ms = _time_plan(binding, descs, n, pixels, k, cells, json.loads(s), flags=flags)
+            ms = _time_plan(binding, descs, n, pixels, k, cells, json.loads(s), flags=flags,
+                            max_width=mw)
             again[s] = min(again[s], ms)
     s_best = min(again, key=again.get)
     if verbose:
@@ -173,9 +192,10 @@ def tune_batch(descs, Hs, Ws, k, cells, budget_s=60.0, verbose=False, flags=0):
     return json.loads(s_best), again[s_best]
 
 
-def save(Hs, Ws, k, cells, tune, ms, path=CACHE, note="", flags=0):
+def save(Hs, Ws, k, cells, tune, ms, path=CACHE, note="", flags=0, windows=False):
     cache = load_cache(path)
-    cache[key(Hs, Ws, k, cells, flags)] = {"tune": tune, "ms": round(ms, 4), "note": note}
+    cache[key(Hs, Ws, k, cells, flags, windows)] = {"tune": tune, "ms": round(ms, 4),
+                                                     "note": note}
     tmp = path + ".tmp%d" % os.getpid()
     with open(tmp, "w") as f:
         json.dump(cache, f, indent=1, sort_keys=True)

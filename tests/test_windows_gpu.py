@@ -187,3 +187,27 @@ def test_cell_plan_more_than_63_cell_columns(lib, cells_x):
         _, h1 = lib.extract(_dev(img), 3, *grid, want_codes=False)
         assert (h1.cpu().numpy().view(np.uint32) == wh).all(), j
     plan.close()
+
+
+@pytest.mark.parametrize("w", [10, 20, 25, 50, 100])
+def test_window_plan_with_cached_tunes(lib, w):
+    """The launch shapes the autotuner cached for window plans of the 490x640
+    batch (smaller workgroups, two window rows per item, short lane tasks)
+    give the oracle's codes and window histograms: 6 frames of that batch."""
+    from paper_1810_11518_amd import autotune
+    Hs, Ws = synth.workload_sizes("batch")
+    tune = autotune.load_cache().get(
+        "gfx950|k3|%dx%d|%dx%d|win" % (w, w, int(Hs[0]), int(Ws[0])), {}).get("tune")
+    assert tune, "no cached window tune for %d px" % w
+    n = 6
+    b = WinBatch(Hs[:n], Ws[:n], synth.WORKLOADS["batch"]["kind"], synth.SEEDS["batch"], (w, w))
+    pixels = int((b.Hs.astype(np.int64) * b.Ws).sum())
+    plan = lib.BatchPlan(n, pixels, 3, w, w, tune, windows=True, max_width=int(Ws[0]))
+    plan.set(lib.BatchPlan.descs(*b.args))
+    plan.run()
+    torch.cuda.synchronize()
+    for j in range(n):
+        wc = oracle_c.ldp_codes(b.image(j), 3)
+        assert (b.codes[j].cpu().numpy().reshape(wc.shape) == wc).all(), j
+        assert (b.hist[j].cpu().numpy().view(np.uint32) == oracle_np.window_histograms(wc, w, w)).all(), j
+    plan.close()
