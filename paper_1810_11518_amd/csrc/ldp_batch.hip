@@ -106,11 +106,13 @@ struct ArgTables {
 // pixels (every image's cell grid follows from its own size).  The item
 // number is broadcast through the LDS word after the histograms (`item_slot`,
 // in words): the kernels have no static LDS, and the histograms start at the
-// beginning of the dynamic LDS.
+// beginning of the dynamic LDS, in `copies` (1 or 2) copies of item_slot /
+// copies words each.
 template <int K, int MODE, class Tables>
 __device__ __forceinline__ void run_queue(const Tables &tab, uint32_t n_items, Meta *meta,
                                           int32_t gy, int32_t gx, int32_t windows,
-                                          int32_t item_slot, const MinRows &min_rows)
+                                          int32_t item_slot, int32_t copies,
+                                          const MinRows &min_rows)
 {
     extern __shared__ uint32_t lds[];
     uint32_t &s_item = lds[item_slot];
@@ -132,7 +134,7 @@ __device__ __forceinline__ void run_queue(const Tables &tab, uint32_t n_items, M
         const int32_t r1 = geom_row_start(geo, w.cy1, im.Hc);
         // a null code pointer gives an empty store range: stores are dropped
         fused_item<K, MODE, true>(im, lds, geo, w.cy0, w.cy1, w.cx0, w.cx1, r0, r1, hist, false,
-                                  task_rows);
+                                  task_rows, copies, item_slot / copies);
     }
     // Every workgroup has taken its last number once all have counted
     // themselves here: the last one resets the queue for the next launch
@@ -147,7 +149,7 @@ template <int K, int MODE>
 __global__ void __launch_bounds__(1024) LDP_BATCH_ATTR batch_kernel(const ldp_image_desc *__restrict__ descs,
                                                      Meta *meta, int32_t gy, int32_t gx,
                                                      int32_t windows, int32_t item_slot,
-                                                     MinRows min_rows)
+                                                     int32_t copies, MinRows min_rows)
 {
     // the item count and table address are the same for every lane:
     // readfirstlane keeps them (and what is read through them) in scalar
@@ -155,7 +157,7 @@ __global__ void __launch_bounds__(1024) LDP_BATCH_ATTR batch_kernel(const ldp_im
     const uint32_t n_items = uniform(meta->n_items);
     const DeviceTables tab{
         (const ConstItem *)(uintptr_t)uniform64(reinterpret_cast<uint64_t>(meta->items)), descs};
-    run_queue<K, MODE>(tab, n_items, meta, gy, gx, windows, item_slot, min_rows);
+    run_queue<K, MODE>(tab, n_items, meta, gy, gx, windows, item_slot, copies, min_rows);
 }
 
 // The same pass over a batch given in the arguments; only the queue counter
@@ -164,12 +166,14 @@ template <int K, int MODE>
 __global__ void __launch_bounds__(1024) LDP_BATCH_ATTR batch_arg_kernel(const ArgBatch b, Meta *meta,
                                                          int32_t gy, int32_t gx,
                                                          int32_t windows, int32_t item_slot,
-                                                         MinRows min_rows)
+                                                         int32_t copies, MinRows min_rows)
 {
-    run_queue<K, MODE>(ArgTables{&b}, b.n_items, meta, gy, gx, windows, item_slot, min_rows);
+    run_queue<K, MODE>(ArgTables{&b}, b.n_items, meta, gy, gx, windows, item_slot, copies,
+                       min_rows);
 }
 
-typedef void (*batch_arg_fn)(const ArgBatch, Meta *, int32_t, int32_t, int32_t, int32_t, MinRows);
+typedef void (*batch_arg_fn)(const ArgBatch, Meta *, int32_t, int32_t, int32_t, int32_t, int32_t,
+                             MinRows);
 
 static batch_arg_fn batch_arg_kernel_for(int k)
 {
@@ -187,7 +191,7 @@ static batch_arg_fn batch_arg_kernel_for(int k)
 }
 
 typedef void (*batch_fn)(const ldp_image_desc *, Meta *, int32_t, int32_t, int32_t, int32_t,
-                         MinRows);
+                         int32_t, MinRows);
 
 template <int MODE>
 static batch_fn batch_kernel_for_mode(int k)
@@ -229,6 +233,7 @@ struct ldp_batch_plan {
     ldp_size_class classes[LDP_MAX_SIZE_CLASSES] = {{INT64_MAX, 1, 8}};
     ldp::MinRows min_rows{};   // classes[c].rows_per_task, as the kernels take them
     size_t lds_bytes = 0;
+    int32_t copies = 1;  // copies of the histograms in LDS (fused_item)
     int device = 0;
     // One device block and its pinned staging mirror, laid out as
     // [meta | descriptors | work items], so that a batch uploads in one copy.
@@ -358,7 +363,12 @@ int create_plan(ldp_batch_plan **out, int32_t max_images, int64_t max_pixels, in
     // LDS: the largest item's cell rows, each with its discard cell, then the
     // item broadcast word (16 bytes keep the allocation aligned)
     const size_t hist_bytes = (size_t)max_cpi * ldp::hist_row_bytes(nx_max);
-    p->lds_bytes = hist_bytes + 16;
+    // two copies of the histograms (even and odd lanes) when they fit the
+    // workgroup's share of the CU's LDS: 32 KB up to 256 threads (five
+    // workgroups per CU), else 64 KB
+    const size_t budget = p->threads <= 256 ? 32768u : 65536u - 16u;
+    p->copies = 2 * hist_bytes <= budget ? 2 : 1;
+    p->lds_bytes = p->copies * hist_bytes + 16;
     if (hipGetDevice(&p->device) != hipSuccess) {
         delete p;
         return LDP_ERR_HIP;
@@ -403,7 +413,7 @@ int create_plan(ldp_batch_plan **out, int32_t max_images, int64_t max_pixels, in
         return fail(LDP_ERR_HIP);
     hipLaunchKernelGGL(fn, dim3(p->grid), dim3(p->threads), p->lds_bytes, p->cap_stream,
                        (const ldp_image_desc *)p->d_descs, p->d_meta, gy, gx, windows ? 1 : 0,
-                       (int32_t)(hist_bytes / 4), p->min_rows);
+                       (int32_t)(p->copies * hist_bytes / 4), p->copies, p->min_rows);
     hipError_t ce = hipStreamEndCapture(p->cap_stream, &p->graph);
     if (ce != hipSuccess || hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) !=
                                 hipSuccess)
@@ -660,9 +670,9 @@ int launch_args(const ldp_batch_plan *p, batch_arg_fn fn, ArgBatch &b, hipStream
     const int32_t grid = (int32_t)std::max<int64_t>(1, std::min<int64_t>(p->grid, b.n_items));
     Meta *meta = p->d_meta;
     int32_t gy = p->gy, gx = p->gx, windows = 0;
-    int32_t item_slot = (int32_t)((p->lds_bytes - 16) / 4);
+    int32_t item_slot = (int32_t)((p->lds_bytes - 16) / 4), copies = p->copies;
     MinRows min_rows = p->min_rows;
-    void *args[] = {&b, &meta, &gy, &gx, &windows, &item_slot, &min_rows};
+    void *args[] = {&b, &meta, &gy, &gx, &windows, &item_slot, &copies, &min_rows};
     return hipLaunchKernel(reinterpret_cast<const void *>(fn), dim3(grid), dim3(p->threads), args,
                            p->lds_bytes, s) == hipSuccess &&
                    hipEventRecord(p->ran, s) == hipSuccess
@@ -853,9 +863,9 @@ extern "C" int ldp_batch_launch_noalloc(const ldp_image_desc *descs, int32_t n, 
     const size_t hist_bytes = hist_row_bytes(run_cells);
     const size_t lds_bytes = hist_bytes + 16;
     int32_t gy = cells_y, gx = cells_x, windows = 0;
-    int32_t item_slot = (int32_t)(hist_bytes / 4);
+    int32_t item_slot = (int32_t)(hist_bytes / 4), copies = 1;
     MinRows min_rows{{kNoallocTaskRows, kNoallocTaskRows, kNoallocTaskRows, kNoallocTaskRows}};
-    void *args[] = {&b, &meta, &gy, &gx, &windows, &item_slot, &min_rows};
+    void *args[] = {&b, &meta, &gy, &gx, &windows, &item_slot, &copies, &min_rows};
     // no more workgroups than items: each takes items until the queue is
     // empty, and the last one out leaves the queue words at zero
     const batch_arg_fn fn = batch_arg_kernel_for(k);

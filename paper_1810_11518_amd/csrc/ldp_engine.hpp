@@ -447,11 +447,18 @@ __device__ void run_task_narrow(const ImgView &im, uint32_t *lds_bins, uint32_t 
 // [0, base) take the q-band groups, column group fastest (neighbouring lanes
 // read neighbouring columns), lanes [base, threads) the (q+1)-band groups.
 // Wider maps (more column groups than threads) take whole cell rows per task.
+//
+// With copies = 2 the LDS holds two copies of the item's histograms,
+// copy_words apart, and even and odd lanes count into different copies:
+// neighbouring lanes (eight columns apart) often give a pixel the same code,
+// and two lanes adding into one LDS word are serialised.  The flush adds the
+// copies.
 template <int K, int MODE, bool CODES>
 __device__ __forceinline__ void fused_item(const ImgView &im, uint32_t *lds, const Geom &geo,
                                            int32_t cy0, int32_t cy1, int32_t cx0, int32_t cx1,
                                            int32_t r0, int32_t r1, uint32_t *hist,
-                                           bool atomic_flush, int32_t min_task_rows)
+                                           bool atomic_flush, int32_t min_task_rows,
+                                           int32_t copies = 1, int32_t copy_words = 0)
 {
     const int tid = threadIdx.x, nthreads = blockDim.x;
     const int32_t ncell = cx1 - cx0;
@@ -460,9 +467,13 @@ __device__ __forceinline__ void fused_item(const ImgView &im, uint32_t *lds, con
     const int32_t c_lo = geom_col_start(geo, cx0, im.Wc), c_hi = geom_col_start(geo, cx1, im.Wc);
     // 16-byte LDS writes (the histograms start 16-byte aligned and every
     // cell row is a multiple of 1 KB)
-    uint4 *lds4 = reinterpret_cast<uint4 *>(lds);
-    for (int32_t i = tid; i < (cy1 - cy0) * (row_words / 4); i += nthreads)
-        lds4[i] = make_uint4(0u, 0u, 0u, 0u);
+    for (int32_t c = 0; c < copies; ++c) {
+        uint4 *lds4 = reinterpret_cast<uint4 *>(lds + c * copy_words);
+        for (int32_t i = tid; i < (cy1 - cy0) * (row_words / 4); i += nthreads)
+            lds4[i] = make_uint4(0u, 0u, 0u, 0u);
+    }
+    // this lane's copy
+    uint32_t *const bins = copies > 1 ? lds + (tid & 1) * copy_words : lds;
     __syncthreads();
     // code rows [a, b) of the current cell row inside [r0, r1)
     int32_t a = max(r0, geom_row_start(geo, cy0, im.Hc));
@@ -478,7 +489,7 @@ __device__ __forceinline__ void fused_item(const ImgView &im, uint32_t *lds, con
                 const int32_t a0 = a + (int32_t)(((uint32_t)nr * tid) / (uint32_t)nsub);
                 const int32_t a1 = a + (int32_t)(((uint32_t)nr * (tid + 1)) / (uint32_t)nsub);
                 if (a1 > a0)
-                    run_task_narrow<K, MODE, true, CODES>(im, lds, (cy - cy0) * row_bytes, geo,
+                    run_task_narrow<K, MODE, true, CODES>(im, bins, (cy - cy0) * row_bytes, geo,
                                                     a0, a1);
             }
         }
@@ -521,7 +532,7 @@ __device__ __forceinline__ void fused_item(const ImgView &im, uint32_t *lds, con
                     const int32_t a0 = a + (int32_t)(qs + udiv_small(rs, nb));
                     const int32_t a1 = a + (int32_t)(qs + qn + udiv_small(rs + rn, nb));
                     if (a1 > a0)
-                        run_task<K, MODE, true, CODES>(im, lds, (cy - cy0) * row_bytes, c, a0, a1);
+                        run_task<K, MODE, true, CODES>(im, bins, (cy - cy0) * row_bytes, c, a0, a1);
                 }
             }
         } else {
@@ -532,7 +543,7 @@ __device__ __forceinline__ void fused_item(const ImgView &im, uint32_t *lds, con
                 }
                 for (int32_t g = tid; g < ngroups; g += nthreads)
                     run_task<K, MODE, true, CODES>(
-                        im, lds, (cy - cy0) * row_bytes,
+                        im, bins, (cy - cy0) * row_bytes,
                         group_cols<true>(geo, g, c_lo, c_hi, cx0, ncell, im.Wc), a, b);
             }
         }
@@ -546,10 +557,11 @@ __device__ __forceinline__ void fused_item(const ImgView &im, uint32_t *lds, con
         typedef __attribute__((address_space(1))) u32x4 global_u32x4;
         for (int32_t r = 0; r < cy1 - cy0; ++r) {
             const u32x4 *src = reinterpret_cast<const u32x4 *>(lds + r * row_words);
+            const u32x4 *src1 = reinterpret_cast<const u32x4 *>(lds + copy_words + r * row_words);
             global_u32x4 *dst =
                 (global_u32x4 *)(hist + ((int64_t)(cy0 + r) * geo.nx + cx0) * 256);
             for (int32_t i = tid; i < ncell * 64; i += nthreads)
-                dst[i] = src[i];
+                dst[i] = copies > 1 ? src[i] + src1[i] : src[i];
         }
         return;
     }
@@ -557,7 +569,7 @@ __device__ __forceinline__ void fused_item(const ImgView &im, uint32_t *lds, con
         const uint32_t *src = lds + r * row_words;
         global_u32 *dst = (global_u32 *)(hist + ((int64_t)(cy0 + r) * geo.nx + cx0) * 256);
         for (int32_t i = tid; i < ncell * 256; i += nthreads) {
-            const uint32_t v = src[i];
+            const uint32_t v = copies > 1 ? src[i] + src[copy_words + i] : src[i];
             if (!atomic_flush)
                 dst[i] = v;
             else if (v)
