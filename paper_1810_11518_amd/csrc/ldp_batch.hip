@@ -106,13 +106,12 @@ struct ArgTables {
 // pixels (every image's cell grid follows from its own size).  The item
 // number is broadcast through the LDS word after the histograms (`item_slot`,
 // in words): the kernels have no static LDS, and the histograms start at the
-// beginning of the dynamic LDS, in `copies` (1 or 2) copies of item_slot /
-// copies words each.
-template <int K, int MODE, class Tables>
+// beginning of the dynamic LDS, in COPIES (1 or 2) copies of item_slot /
+// COPIES words each.
+template <int K, int MODE, int COPIES, class Tables>
 __device__ __forceinline__ void run_queue(const Tables &tab, uint32_t n_items, Meta *meta,
                                           int32_t gy, int32_t gx, int32_t windows,
-                                          int32_t item_slot, int32_t copies,
-                                          const MinRows &min_rows)
+                                          int32_t item_slot, const MinRows &min_rows)
 {
     extern __shared__ uint32_t lds[];
     uint32_t &s_item = lds[item_slot];
@@ -133,8 +132,8 @@ __device__ __forceinline__ void run_queue(const Tables &tab, uint32_t n_items, M
         const int32_t r0 = geom_row_start(geo, w.cy0, im.Hc);
         const int32_t r1 = geom_row_start(geo, w.cy1, im.Hc);
         // a null code pointer gives an empty store range: stores are dropped
-        fused_item<K, MODE, true>(im, lds, geo, w.cy0, w.cy1, w.cx0, w.cx1, r0, r1, hist, false,
-                                  task_rows, copies, item_slot / copies);
+        fused_item<K, MODE, true, COPIES>(im, lds, geo, w.cy0, w.cy1, w.cx0, w.cx1, r0, r1,
+                                          hist, false, task_rows, item_slot / COPIES);
     }
     // Every workgroup has taken its last number once all have counted
     // themselves here: the last one resets the queue for the next launch
@@ -145,11 +144,11 @@ __device__ __forceinline__ void run_queue(const Tables &tab, uint32_t n_items, M
     }
 }
 
-template <int K, int MODE>
+template <int K, int MODE, int COPIES>
 __global__ void __launch_bounds__(1024) LDP_BATCH_ATTR batch_kernel(const ldp_image_desc *__restrict__ descs,
                                                      Meta *meta, int32_t gy, int32_t gx,
                                                      int32_t windows, int32_t item_slot,
-                                                     int32_t copies, MinRows min_rows)
+                                                     MinRows min_rows)
 {
     // the item count and table address are the same for every lane:
     // readfirstlane keeps them (and what is read through them) in scalar
@@ -157,66 +156,80 @@ __global__ void __launch_bounds__(1024) LDP_BATCH_ATTR batch_kernel(const ldp_im
     const uint32_t n_items = uniform(meta->n_items);
     const DeviceTables tab{
         (const ConstItem *)(uintptr_t)uniform64(reinterpret_cast<uint64_t>(meta->items)), descs};
-    run_queue<K, MODE>(tab, n_items, meta, gy, gx, windows, item_slot, copies, min_rows);
+    run_queue<K, MODE, COPIES>(tab, n_items, meta, gy, gx, windows, item_slot, min_rows);
 }
 
 // The same pass over a batch given in the arguments; only the queue counter
 // is read from device memory.
-template <int K, int MODE>
+template <int K, int MODE, int COPIES>
 __global__ void __launch_bounds__(1024) LDP_BATCH_ATTR batch_arg_kernel(const ArgBatch b, Meta *meta,
                                                          int32_t gy, int32_t gx,
                                                          int32_t windows, int32_t item_slot,
-                                                         int32_t copies, MinRows min_rows)
+                                                         MinRows min_rows)
 {
-    run_queue<K, MODE>(ArgTables{&b}, b.n_items, meta, gy, gx, windows, item_slot, copies,
-                       min_rows);
+    run_queue<K, MODE, COPIES>(ArgTables{&b}, b.n_items, meta, gy, gx, windows, item_slot,
+                               min_rows);
 }
 
-typedef void (*batch_arg_fn)(const ArgBatch, Meta *, int32_t, int32_t, int32_t, int32_t, int32_t,
-                             MinRows);
+typedef void (*batch_arg_fn)(const ArgBatch, Meta *, int32_t, int32_t, int32_t, int32_t, MinRows);
 
-static batch_arg_fn batch_arg_kernel_for(int k)
+template <int COPIES>
+static batch_arg_fn batch_arg_kernel_for_copies(int k)
 {
     switch (k) {
-    case 1: return batch_arg_kernel<1, RANK_SIGNED>;
-    case 2: return batch_arg_kernel<2, RANK_SIGNED>;
-    case 3: return batch_arg_kernel<3, RANK_SIGNED>;
-    case 4: return batch_arg_kernel<4, RANK_SIGNED>;
-    case 5: return batch_arg_kernel<5, RANK_SIGNED>;
-    case 6: return batch_arg_kernel<6, RANK_SIGNED>;
-    case 7: return batch_arg_kernel<7, RANK_SIGNED>;
-    case 8: return batch_arg_kernel<8, RANK_SIGNED>;
+    case 1: return batch_arg_kernel<1, RANK_SIGNED, COPIES>;
+    case 2: return batch_arg_kernel<2, RANK_SIGNED, COPIES>;
+    case 3: return batch_arg_kernel<3, RANK_SIGNED, COPIES>;
+    case 4: return batch_arg_kernel<4, RANK_SIGNED, COPIES>;
+    case 5: return batch_arg_kernel<5, RANK_SIGNED, COPIES>;
+    case 6: return batch_arg_kernel<6, RANK_SIGNED, COPIES>;
+    case 7: return batch_arg_kernel<7, RANK_SIGNED, COPIES>;
+    case 8: return batch_arg_kernel<8, RANK_SIGNED, COPIES>;
     }
     return nullptr;
+}
+
+static batch_arg_fn batch_arg_kernel_for(int k, int copies = 1)
+{
+    return copies == 2 ? batch_arg_kernel_for_copies<2>(k) : batch_arg_kernel_for_copies<1>(k);
 }
 
 typedef void (*batch_fn)(const ldp_image_desc *, Meta *, int32_t, int32_t, int32_t, int32_t,
-                         int32_t, MinRows);
+                         MinRows);
 
-template <int MODE>
+template <int MODE, int COPIES>
 static batch_fn batch_kernel_for_mode(int k)
 {
     switch (k) {
-    case 1: return batch_kernel<1, MODE>;
-    case 2: return batch_kernel<2, MODE>;
-    case 3: return batch_kernel<3, MODE>;
-    case 4: return batch_kernel<4, MODE>;
-    case 5: return batch_kernel<5, MODE>;
-    case 6: return batch_kernel<6, MODE>;
-    case 7: return batch_kernel<7, MODE>;
-    case 8: return batch_kernel<8, MODE>;
+    case 1: return batch_kernel<1, MODE, COPIES>;
+    case 2: return batch_kernel<2, MODE, COPIES>;
+    case 3: return batch_kernel<3, MODE, COPIES>;
+    case 4: return batch_kernel<4, MODE, COPIES>;
+    case 5: return batch_kernel<5, MODE, COPIES>;
+    case 6: return batch_kernel<6, MODE, COPIES>;
+    case 7: return batch_kernel<7, MODE, COPIES>;
+    case 8: return batch_kernel<8, MODE, COPIES>;
     }
     return nullptr;
 }
 
-static batch_fn batch_kernel_for(int k, int mode)
+template <int COPIES>
+static batch_fn batch_kernel_for_copies(int k, int mode)
 {
     switch (mode) {
-    case RANK_MAGNITUDE: return batch_kernel_for_mode<RANK_MAGNITUDE>(k);
-    case DIRECT_MASKS: return batch_kernel_for_mode<DIRECT_MASKS>(k);
-    case CODE_LBP: return batch_kernel<1, CODE_LBP>;  // LBP codes do not depend on k
+    case RANK_MAGNITUDE: return batch_kernel_for_mode<RANK_MAGNITUDE, COPIES>(k);
+    case DIRECT_MASKS: return batch_kernel_for_mode<DIRECT_MASKS, COPIES>(k);
+    case CODE_LBP: return batch_kernel<1, CODE_LBP, COPIES>;  // LBP codes do not depend on k
     }
-    return batch_kernel_for_mode<RANK_SIGNED>(k);
+    return batch_kernel_for_mode<RANK_SIGNED, COPIES>(k);
+}
+
+// The batch kernel for k, the ranking mode and one or two LDS copies of the
+// histograms (a template argument: each kernel holds one form, whose
+// registers and schedule are not shared with the other).
+static batch_fn batch_kernel_for(int k, int mode, int copies = 1)
+{
+    return copies == 2 ? batch_kernel_for_copies<2>(k, mode) : batch_kernel_for_copies<1>(k, mode);
 }
 
 }  // namespace ldp
@@ -363,15 +376,32 @@ int create_plan(ldp_batch_plan **out, int32_t max_images, int64_t max_pixels, in
     // LDS: the largest item's cell rows, each with its discard cell, then the
     // item broadcast word (16 bytes keep the allocation aligned)
     const size_t hist_bytes = (size_t)max_cpi * ldp::hist_row_bytes(nx_max);
-    // two copies of the histograms (even and odd lanes) when they fit the
-    // workgroup's share of the CU's LDS: 32 KB up to 256 threads (five
-    // workgroups per CU), else 64 KB
-    const size_t budget = p->threads <= 256 ? 32768u : 65536u - 16u;
-    p->copies = 2 * hist_bytes <= budget ? 2 : 1;
-    p->lds_bytes = p->copies * hist_bytes + 16;
+    p->lds_bytes = hist_bytes + 16;
     if (hipGetDevice(&p->device) != hipSuccess) {
         delete p;
         return LDP_ERR_HIP;
+    }
+    // Cell-grid plans: two copies of the histograms (even and odd lanes)
+    // when that kernel, with the LDS they take, keeps as many workgroups on a
+    // CU as the one-copy kernel (registers usually decide that number, and
+    // the copies use LDS left over).  Window plans keep one copy (their
+    // rows of windows fill the LDS).
+    ldp::batch_fn fn = ldp::batch_kernel_for(k, ldp::rank_mode(flags), 1);
+    if (!windows) {
+        ldp::batch_fn fn2 = ldp::batch_kernel_for(k, ldp::rank_mode(flags), 2);
+        int occ1 = 0, occ2 = 0;
+        const size_t lds2 = 2 * hist_bytes + 16;
+        if (lds2 <= 65536u &&
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ1, reinterpret_cast<const void *>(fn),
+                                                         p->threads, p->lds_bytes) == hipSuccess &&
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ2, reinterpret_cast<const void *>(fn2),
+                                                         p->threads, lds2) == hipSuccess &&
+            occ2 > 0 && occ2 >= occ1) {
+            p->copies = 2;
+            p->lds_bytes = lds2;
+            fn = fn2;
+        }
+        (void)hipGetLastError();
     }
     auto fail = [&](int st) {
         release(p);
@@ -393,7 +423,6 @@ int create_plan(ldp_batch_plan **out, int32_t max_images, int64_t max_pixels, in
     if (hipMemset(p->d_meta, 0, sizeof(ldp::Meta)) != hipSuccess)
         return fail(LDP_ERR_HIP);
 
-    ldp::batch_fn fn = ldp::batch_kernel_for(k, ldp::rank_mode(flags));
     if (!p->grid) {
         int per_cu = 0, cus = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(fn),
@@ -413,7 +442,7 @@ int create_plan(ldp_batch_plan **out, int32_t max_images, int64_t max_pixels, in
         return fail(LDP_ERR_HIP);
     hipLaunchKernelGGL(fn, dim3(p->grid), dim3(p->threads), p->lds_bytes, p->cap_stream,
                        (const ldp_image_desc *)p->d_descs, p->d_meta, gy, gx, windows ? 1 : 0,
-                       (int32_t)(p->copies * hist_bytes / 4), p->copies, p->min_rows);
+                       (int32_t)(p->copies * hist_bytes / 4), p->min_rows);
     hipError_t ce = hipStreamEndCapture(p->cap_stream, &p->graph);
     if (ce != hipSuccess || hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) !=
                                 hipSuccess)
@@ -659,7 +688,7 @@ namespace {
 // batches always go through the loaded tables: windows, or flags).
 batch_arg_fn arg_kernel(const ldp_batch_plan *p)
 {
-    return !p->windows && rank_mode(p->flags) == RANK_SIGNED ? batch_arg_kernel_for(p->k)
+    return !p->windows && rank_mode(p->flags) == RANK_SIGNED ? batch_arg_kernel_for(p->k, p->copies)
                                                              : nullptr;
 }
 
@@ -670,9 +699,9 @@ int launch_args(const ldp_batch_plan *p, batch_arg_fn fn, ArgBatch &b, hipStream
     const int32_t grid = (int32_t)std::max<int64_t>(1, std::min<int64_t>(p->grid, b.n_items));
     Meta *meta = p->d_meta;
     int32_t gy = p->gy, gx = p->gx, windows = 0;
-    int32_t item_slot = (int32_t)((p->lds_bytes - 16) / 4), copies = p->copies;
+    int32_t item_slot = (int32_t)((p->lds_bytes - 16) / 4);
     MinRows min_rows = p->min_rows;
-    void *args[] = {&b, &meta, &gy, &gx, &windows, &item_slot, &copies, &min_rows};
+    void *args[] = {&b, &meta, &gy, &gx, &windows, &item_slot, &min_rows};
     return hipLaunchKernel(reinterpret_cast<const void *>(fn), dim3(grid), dim3(p->threads), args,
                            p->lds_bytes, s) == hipSuccess &&
                    hipEventRecord(p->ran, s) == hipSuccess
@@ -863,9 +892,9 @@ extern "C" int ldp_batch_launch_noalloc(const ldp_image_desc *descs, int32_t n, 
     const size_t hist_bytes = hist_row_bytes(run_cells);
     const size_t lds_bytes = hist_bytes + 16;
     int32_t gy = cells_y, gx = cells_x, windows = 0;
-    int32_t item_slot = (int32_t)(hist_bytes / 4), copies = 1;
+    int32_t item_slot = (int32_t)(hist_bytes / 4);
     MinRows min_rows{{kNoallocTaskRows, kNoallocTaskRows, kNoallocTaskRows, kNoallocTaskRows}};
-    void *args[] = {&b, &meta, &gy, &gx, &windows, &item_slot, &copies, &min_rows};
+    void *args[] = {&b, &meta, &gy, &gx, &windows, &item_slot, &min_rows};
     // no more workgroups than items: each takes items until the queue is
     // empty, and the last one out leaves the queue words at zero
     const batch_arg_fn fn = batch_arg_kernel_for(k);

@@ -448,18 +448,20 @@ __device__ void run_task_narrow(const ImgView &im, uint32_t *lds_bins, uint32_t 
 // read neighbouring columns), lanes [base, threads) the (q+1)-band groups.
 // Wider maps (more column groups than threads) take whole cell rows per task.
 //
-// With copies = 2 the LDS holds two copies of the item's histograms,
+// With COPIES = 2 the LDS holds two copies of the item's histograms,
 // copy_words apart, and even and odd lanes count into different copies:
 // neighbouring lanes (eight columns apart) often give a pixel the same code,
 // and two lanes adding into one LDS word are serialised.  The flush adds the
-// copies.
-template <int K, int MODE, bool CODES>
+// copies.  (A compile-time count: with one copy the code is that of a single
+// set of histograms, whose per-item work small items feel.)
+template <int K, int MODE, bool CODES, int COPIES = 1>
 __device__ __forceinline__ void fused_item(const ImgView &im, uint32_t *lds, const Geom &geo,
                                            int32_t cy0, int32_t cy1, int32_t cx0, int32_t cx1,
                                            int32_t r0, int32_t r1, uint32_t *hist,
                                            bool atomic_flush, int32_t min_task_rows,
-                                           int32_t copies = 1, int32_t copy_words = 0)
+                                           int32_t copy_words = 0)
 {
+    static_assert(COPIES == 1 || COPIES == 2, "one or two copies");
     const int tid = threadIdx.x, nthreads = blockDim.x;
     const int32_t ncell = cx1 - cx0;
     const uint32_t row_bytes = hist_row_bytes(ncell);
@@ -467,13 +469,14 @@ __device__ __forceinline__ void fused_item(const ImgView &im, uint32_t *lds, con
     const int32_t c_lo = geom_col_start(geo, cx0, im.Wc), c_hi = geom_col_start(geo, cx1, im.Wc);
     // 16-byte LDS writes (the histograms start 16-byte aligned and every
     // cell row is a multiple of 1 KB)
-    for (int32_t c = 0; c < copies; ++c) {
+#pragma unroll
+    for (int32_t c = 0; c < COPIES; ++c) {
         uint4 *lds4 = reinterpret_cast<uint4 *>(lds + c * copy_words);
         for (int32_t i = tid; i < (cy1 - cy0) * (row_words / 4); i += nthreads)
             lds4[i] = make_uint4(0u, 0u, 0u, 0u);
     }
     // this lane's copy
-    uint32_t *const bins = copies > 1 ? lds + (tid & 1) * copy_words : lds;
+    uint32_t *const bins = COPIES > 1 ? lds + (tid & 1) * copy_words : lds;
     __syncthreads();
     // code rows [a, b) of the current cell row inside [r0, r1)
     int32_t a = max(r0, geom_row_start(geo, cy0, im.Hc));
@@ -561,7 +564,7 @@ __device__ __forceinline__ void fused_item(const ImgView &im, uint32_t *lds, con
             global_u32x4 *dst =
                 (global_u32x4 *)(hist + ((int64_t)(cy0 + r) * geo.nx + cx0) * 256);
             for (int32_t i = tid; i < ncell * 64; i += nthreads)
-                dst[i] = copies > 1 ? src[i] + src1[i] : src[i];
+                dst[i] = COPIES > 1 ? src[i] + src1[i] : src[i];
         }
         return;
     }
@@ -569,7 +572,7 @@ __device__ __forceinline__ void fused_item(const ImgView &im, uint32_t *lds, con
         const uint32_t *src = lds + r * row_words;
         global_u32 *dst = (global_u32 *)(hist + ((int64_t)(cy0 + r) * geo.nx + cx0) * 256);
         for (int32_t i = tid; i < ncell * 256; i += nthreads) {
-            const uint32_t v = copies > 1 ? src[i] + src[copy_words + i] : src[i];
+            const uint32_t v = COPIES > 1 ? src[i] + src[copy_words + i] : src[i];
             if (!atomic_flush)
                 dst[i] = v;
             else if (v)

@@ -34,14 +34,15 @@ def _blocks(body):
     return out
 
 
-def main_loop_valu(asm, k, mode):
-    """Fewest VALU instructions of any main row loop of batch_kernel<k, mode>:
-    the innermost loops that hold 24 LDS instructions (the x3-unrolled row
-    loop, 8 per row step).  Each task layout has one such loop for waves whose
-    rows all start 4-aligned and one for the rest; the aligned one, which most
-    waves run, has the fewest."""
-    m = re.search(r"^(_ZN3ldp12batch_kernelILi%dELi%dEEEv\w*):" % (k, mode), asm, re.M)
-    assert m, "batch_kernel<%d, %d> not found" % (k, mode)
+def main_loop_valu(asm, k, mode, copies=1):
+    """Fewest VALU instructions of any main row loop of batch_kernel<k, mode,
+    copies>: the innermost loops that hold 24 LDS instructions (the
+    x3-unrolled row loop, 8 per row step).  Each task layout has one such loop
+    for waves whose rows all start 4-aligned and one for the rest; the aligned
+    one, which most waves run, has the fewest."""
+    m = re.search(r"^(_ZN3ldp12batch_kernelILi%dELi%dELi%dEEEv\w*):" % (k, mode, copies), asm,
+                  re.M)
+    assert m, "batch_kernel<%d, %d, %d> not found" % (k, mode, copies)
     i = m.start()
     body = asm[i:asm.index(".Lfunc_end", i)]
     blocks = _blocks(body)
@@ -66,9 +67,12 @@ def test_valu_per_row_step_matches_generated_code(tmp_path):
     p = subprocess.run(cmd, capture_output=True, text=True)
     assert p.returncode == 0, p.stderr[-2000:]
     asm = open(out).read()
-    for mode, table in ((0, bench.VALU_PER_ROW_STEP), (1, bench.VALU_PER_ROW_STEP_MAGNITUDE),
-                        (2, bench.VALU_PER_ROW_STEP_DIRECT)):
-        for k in range(1, 9):
-            n = main_loop_valu(asm, k, mode)
-            assert table[k] * 3 == pytest.approx(n), (mode, k, n)
-    assert bench.VALU_PER_ROW_STEP_LBP * 3 == pytest.approx(main_loop_valu(asm, 1, 3))
+    # the kernels with one and with two LDS copies of the histograms share
+    # the row loop
+    for copies in (1, 2):
+        for mode, table in ((0, bench.VALU_PER_ROW_STEP), (1, bench.VALU_PER_ROW_STEP_MAGNITUDE),
+                            (2, bench.VALU_PER_ROW_STEP_DIRECT)):
+            for k in range(1, 9):
+                n = main_loop_valu(asm, k, mode, copies)
+                assert table[k] * 3 == pytest.approx(n), (mode, k, copies, n)
+        assert bench.VALU_PER_ROW_STEP_LBP * 3 == pytest.approx(main_loop_valu(asm, 1, 3, copies))
