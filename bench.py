@@ -230,6 +230,7 @@ def measure_workload(torch, binding, autotune, b, k, steps, plain_steps):
     plan = binding.BatchPlan(b.n, b.pixels, k, b.cells[0], b.cells[1], tune)
     plan.set(b.descs)
     items, grid = plan.info()
+    _, _, hist_copies = plan.layout()
     ms = _timed(torch, plan.run, steps, settle_s=DEVICE_WARMUP_S)
     ms_plain = _timed(torch, plan.run_per_image, plain_steps, warmup=1) if plain_steps else None
     plan.run()
@@ -240,7 +241,7 @@ def measure_workload(torch, binding, autotune, b, k, steps, plain_steps):
            "unit": "Mpixel/s", "hbm": hbm(b.abytes, ms),
            "valu_single_issue_frac": round(VALU_PER_ROW_STEP[k] / 8.0 * code_pixels /
                                            (ms * 1e-3) / 1e12 / VALU_SINGLE_ISSUE_T, 4),
-           "work_items": items, "grid_blocks": grid,
+           "work_items": items, "grid_blocks": grid, "lds_histogram_copies": hist_copies,
            "tune": tune, "tune_source": "autotune cache" if tune else "default"}
     if ms_plain:
         out["plain"] = {"ms": round(ms_plain, 3),
@@ -580,6 +581,7 @@ def main():
     plan = binding.BatchPlan(n, b.pixels, k, cells[0], cells[1], tune)
     plan.set(b.descs)
     items, grid = plan.info()
+    _, lds_bytes, hist_copies = plan.layout()
     stream = torch.cuda.current_stream()
 
     # ---- batched persistent launch (graph replays on torch's current stream)
@@ -689,7 +691,9 @@ def main():
                    "device_warmup_s": DEVICE_WARMUP_S},
         "roofline": {"bound": "hbm", "achieved": roof["achieved"], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": roof["frac"], "traffic": traffic,
-                     "kernel": "batch_kernel<%d, 0>" % k, "kernel_ms": round(ms_event, 4),
+                     "kernel": "batch_kernel<%d, 0, %d>" % (k, hist_copies),
+                     "kernel_ms": round(ms_event, 4),
+                     "lds_bytes_per_workgroup": lds_bytes, "lds_histogram_copies": hist_copies,
                      "algorithmic_bytes_per_launch": b.abytes,
                      "copy": {"achieved": round(copy_gbs, 1), "unit": "GB/s",
                               "frac_of_peak": round(copy_gbs / HBM_PEAK_GBS, 4),

@@ -32,7 +32,7 @@ EXPORTED = [
     "ldp_window_grid", "ldp_histograms_windows", "ldp_extract_windows",
     "ldp_batch_plan_create", "ldp_batch_plan_create_ex", "ldp_batch_plan_create_windows",
     "ldp_batch_plan_set", "ldp_batch_run", "ldp_batch_launch", "ldp_batch_run_per_image",
-    "ldp_batch_plan_info", "ldp_batch_plan_destroy",
+    "ldp_batch_plan_info", "ldp_batch_plan_layout", "ldp_batch_plan_destroy",
     "ldp_now", "ldp_server_create", "ldp_server_submit", "ldp_server_poll",
     "ldp_server_stats_get", "ldp_server_destroy", "ldp_stream_copy", "ldp_batch_launch_noalloc",
 ]
@@ -150,6 +150,8 @@ def load():
         "ldp_batch_launch": (ctypes.c_int, [p, ctypes.POINTER(ImageDesc), i32, p]),
         "ldp_batch_run_per_image": (ctypes.c_int, [p, p]),
         "ldp_batch_plan_info": (ctypes.c_int, [p, ctypes.POINTER(i64), ctypes.POINTER(i32)]),
+        "ldp_batch_plan_layout": (ctypes.c_int, [p, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                                 ctypes.POINTER(i32)]),
         "ldp_batch_plan_destroy": (ctypes.c_int, [p]),
         "ldp_now": (ctypes.c_double, []),
         "ldp_server_create": (ctypes.c_int, [ctypes.POINTER(p), ctypes.POINTER(ServerConfig)]),
@@ -383,6 +385,13 @@ class BatchPlan:
         _check(self._lib.ldp_batch_plan_info(self._plan, ctypes.byref(items), ctypes.byref(grid)),
                "ldp_batch_plan_info")
         return int(items.value), int(grid.value)
+
+    def layout(self):
+        """(threads per workgroup, LDS bytes per workgroup, histogram copies)."""
+        th, lds, cp = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(self._lib.ldp_batch_plan_layout(self._plan, ctypes.byref(th), ctypes.byref(lds),
+                                               ctypes.byref(cp)), "ldp_batch_plan_layout")
+        return int(th.value), int(lds.value), int(cp.value)
 
     def close(self):
         if self._plan:

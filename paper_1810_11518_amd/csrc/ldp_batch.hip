@@ -666,6 +666,20 @@ int ldp_batch_plan_info(const ldp_batch_plan *p, int64_t *work_items, int32_t *g
     return LDP_OK;
 }
 
+int ldp_batch_plan_layout(const ldp_batch_plan *p, int32_t *threads, int32_t *lds_bytes,
+                          int32_t *hist_copies)
+{
+    if (!p)
+        return LDP_ERR_INVALID_ARG;
+    if (threads)
+        *threads = p->threads;
+    if (lds_bytes)
+        *lds_bytes = (int32_t)p->lds_bytes;
+    if (hist_copies)
+        *hist_copies = p->copies;
+    return LDP_OK;
+}
+
 int ldp_batch_plan_destroy(ldp_batch_plan *p)
 {
     if (!p)
