@@ -106,8 +106,8 @@ struct ArgTables {
 // pixels (every image's cell grid follows from its own size).  The item
 // number is broadcast through the LDS word after the histograms (`item_slot`,
 // in words): the kernels have no static LDS, and the histograms start at the
-// beginning of the dynamic LDS, in COPIES (1 or 2) copies of item_slot /
-// COPIES words each.
+// beginning of the dynamic LDS, in COPIES (1 or 2) copies item_slot /
+// COPIES words apart.
 template <int K, int MODE, int COPIES, class Tables>
 __device__ __forceinline__ void run_queue(const Tables &tab, uint32_t n_items, Meta *meta,
                                           int32_t gy, int32_t gx, int32_t windows,
@@ -385,12 +385,15 @@ int create_plan(ldp_batch_plan **out, int32_t max_images, int64_t max_pixels, in
     // when that kernel, with the LDS they take, keeps as many workgroups on a
     // CU as the one-copy kernel (registers usually decide that number, and
     // the copies use LDS left over).  Window plans keep one copy (their
-    // rows of windows fill the LDS).
+    // rows of windows fill the LDS).  The second copy starts 16 words (16
+    // banks) past the end of the first: the histograms are a multiple of 64
+    // words long, so without the gap an even and an odd lane adding into the
+    // same bin would still address one bank.
     ldp::batch_fn fn = ldp::batch_kernel_for(k, ldp::rank_mode(flags), 1);
     if (!windows) {
         ldp::batch_fn fn2 = ldp::batch_kernel_for(k, ldp::rank_mode(flags), 2);
         int occ1 = 0, occ2 = 0;
-        const size_t lds2 = 2 * hist_bytes + 16;
+        const size_t lds2 = 2 * (hist_bytes + 64) + 16;
         if (lds2 <= 65536u &&
             hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ1, reinterpret_cast<const void *>(fn),
                                                          p->threads, p->lds_bytes) == hipSuccess &&
@@ -442,7 +445,7 @@ int create_plan(ldp_batch_plan **out, int32_t max_images, int64_t max_pixels, in
         return fail(LDP_ERR_HIP);
     hipLaunchKernelGGL(fn, dim3(p->grid), dim3(p->threads), p->lds_bytes, p->cap_stream,
                        (const ldp_image_desc *)p->d_descs, p->d_meta, gy, gx, windows ? 1 : 0,
-                       (int32_t)(p->copies * hist_bytes / 4), p->min_rows);
+                       (int32_t)((p->lds_bytes - 16) / 4), p->min_rows);
     hipError_t ce = hipStreamEndCapture(p->cap_stream, &p->graph);
     if (ce != hipSuccess || hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) !=
                                 hipSuccess)

@@ -327,7 +327,9 @@ def test_plan_layout_histogram_copies(lib):
         plan = _plan(lib, b, 3, (7, 6), dict(block_threads=256,
                                               classes=[dict(cell_rows_per_item=cpi)]))
         th, lds, cp = plan.layout()
-        assert (th, cp) == (256, copies) and lds == copies * cpi * row + 16, (cpi, th, lds, cp)
+        # two copies: the second starts 64 bytes (16 banks) past the first's end
+        slot = cpi * row + (64 if copies == 2 else 0)
+        assert (th, cp) == (256, copies) and lds == copies * slot + 16, (cpi, th, lds, cp)
         plan.run()
         torch.cuda.synchronize()
         for j in range(len(Hs)):
