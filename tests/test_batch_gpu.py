@@ -339,3 +339,38 @@ def test_plan_layout_histogram_copies(lib):
                         max_width=640)
     assert win.layout()[2] == 1
     win.close()
+
+
+def _stripes(H, W, period, seed):
+    """Vertical stripes (columns cycling through `period` levels) with a few
+    noisy rows: every lane of a wave sees the same short cycle of codes, so
+    a wave's LDS adds land on the same few bins (the worst case for the
+    histogram updates, and not the equal-codes fast path)."""
+    r = np.random.default_rng(seed)
+    levels = r.integers(0, 256, period).astype(np.uint8)
+    img = np.broadcast_to(levels[np.arange(W) % period], (H, W)).copy()
+    rows = r.integers(0, H, max(1, H // 50))
+    img[rows] = r.integers(0, 256, (len(rows), W), dtype=np.uint8)
+    return img
+
+
+@pytest.mark.parametrize("k", [2, 3, 4])
+def test_histogram_copies_under_same_bin_contention(lib, k):
+    """One and two LDS copies of the histograms give the oracle's codes and
+    histograms on images where every lane adds into the same few bins."""
+    Hs, Ws = [490, 490, 333, 490], [640, 640, 517, 640]
+    b = Batch(Hs, Ws, synth.KIND_BLUR_RECTS, 90 + k, (7, 6), row_align=4)
+    for j, period in enumerate((2, 3, 2, 5)):
+        b.image(j)[:, :] = _stripes(Hs[j], Ws[j], period, 100 * k + j)
+    b.dev.copy_(torch.from_numpy(b.host))
+    for cpi, copies in ((2, 2), (4, 1)):
+        for h in b.hist:
+            h.fill_(7)
+        plan = _plan(lib, b, k, (7, 6), dict(block_threads=256,
+                                              classes=[dict(cell_rows_per_item=cpi)]))
+        assert plan.layout()[2] == copies
+        plan.run()
+        torch.cuda.synchronize()
+        for j in range(len(Hs)):
+            b.check(j, k, (7, 6))
+        plan.close()
