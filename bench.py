@@ -230,7 +230,7 @@ def measure_workload(torch, binding, autotune, b, k, steps, plain_steps):
     plan = binding.BatchPlan(b.n, b.pixels, k, b.cells[0], b.cells[1], tune)
     plan.set(b.descs)
     items, grid = plan.info()
-    _, _, hist_copies = plan.layout()
+    _, _, hist_copies, _ = plan.layout()
     ms = _timed(torch, plan.run, steps, settle_s=DEVICE_WARMUP_S)
     ms_plain = _timed(torch, plan.run_per_image, plain_steps, warmup=1) if plain_steps else None
     plan.run()
@@ -344,11 +344,13 @@ def variant_bench(binding, torch, args, b, k, tune, ms_signed, sample, saved):
         plan = binding.BatchPlan(b.n, b.pixels, k, w, w, wtune, windows=True, max_width=max_w)
         plan.set(wdescs)
         items, _ = plan.info()
+        nt_stores = plan.layout()[3]
         ms = _timed(torch, plan.run, args.variant_steps)
         plan.close()
         wb = int((b.Hs.astype(np.int64) * b.Ws).sum() + b.code_pixels + nbins.sum() * 4)
         wins.append({"window": w, "windows_per_image": int(ny[0] * nx[0]),
                      "windows": int((ny * nx).sum()), "work_items": items, "tune": wtune,
+                     "non_temporal_stores": bool(nt_stores),
                      "ms": round(ms, 4),
                      "value": round(b.pixels / (ms * 1e-3) / 1e6, 1), "unit": "Mpixel/s",
                      "hbm": hbm(wb, ms)})
@@ -581,7 +583,7 @@ def main():
     plan = binding.BatchPlan(n, b.pixels, k, cells[0], cells[1], tune)
     plan.set(b.descs)
     items, grid = plan.info()
-    _, lds_bytes, hist_copies = plan.layout()
+    _, lds_bytes, hist_copies, _ = plan.layout()
     stream = torch.cuda.current_stream()
 
     # ---- batched persistent launch (graph replays on torch's current stream)

@@ -309,12 +309,14 @@ int ldp_batch_run_per_image(ldp_batch_plan *plan, ldp_stream_t stream);
  * batch (either pointer may be NULL). */
 int ldp_batch_plan_info(const ldp_batch_plan *plan, int64_t *work_items, int32_t *grid_blocks);
 
-/* ldp_batch_plan_layout -- the plan's launch shape: threads per workgroup,
- * LDS bytes per workgroup and the copies (1 or 2) of an item's histograms in
- * that LDS, which the plan chose at creation (two when the kernel keeps as
- * many workgroups per CU with them; any pointer may be NULL). */
+/* ldp_batch_plan_layout -- the plan's launch shape, chosen at creation:
+ * threads per workgroup, LDS bytes per workgroup, the copies (1 or 2) of an
+ * item's histograms in that LDS (two when the kernel keeps as many workgroups
+ * per CU with them), and 1 when its code and histogram stores are
+ * non-temporal (window plans of windows of at most 1024 pixels), else 0.
+ * Any pointer may be NULL. */
 int ldp_batch_plan_layout(const ldp_batch_plan *plan, int32_t *threads, int32_t *lds_bytes,
-                          int32_t *hist_copies);
+                          int32_t *hist_copies, int32_t *nt_stores);
 
 /* ldp_batch_plan_destroy -- release the plan (waits for the plan's last
  * launch and last upload, not for other work on the device). */

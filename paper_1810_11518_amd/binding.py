@@ -151,7 +151,7 @@ def load():
         "ldp_batch_run_per_image": (ctypes.c_int, [p, p]),
         "ldp_batch_plan_info": (ctypes.c_int, [p, ctypes.POINTER(i64), ctypes.POINTER(i32)]),
         "ldp_batch_plan_layout": (ctypes.c_int, [p, ctypes.POINTER(i32), ctypes.POINTER(i32),
-                                                 ctypes.POINTER(i32)]),
+                                                 ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         "ldp_batch_plan_destroy": (ctypes.c_int, [p]),
         "ldp_now": (ctypes.c_double, []),
         "ldp_server_create": (ctypes.c_int, [ctypes.POINTER(p), ctypes.POINTER(ServerConfig)]),
@@ -387,11 +387,13 @@ class BatchPlan:
         return int(items.value), int(grid.value)
 
     def layout(self):
-        """(threads per workgroup, LDS bytes per workgroup, histogram copies)."""
-        th, lds, cp = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        """(threads per workgroup, LDS bytes per workgroup, histogram copies,
+        non-temporal stores as 0 or 1)."""
+        th, lds, cp, nt = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         _check(self._lib.ldp_batch_plan_layout(self._plan, ctypes.byref(th), ctypes.byref(lds),
-                                               ctypes.byref(cp)), "ldp_batch_plan_layout")
-        return int(th.value), int(lds.value), int(cp.value)
+                                               ctypes.byref(cp), ctypes.byref(nt)),
+               "ldp_batch_plan_layout")
+        return int(th.value), int(lds.value), int(cp.value), int(nt.value)
 
     def close(self):
         if self._plan:

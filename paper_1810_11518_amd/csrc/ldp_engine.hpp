@@ -277,6 +277,9 @@ __device__ __forceinline__ void lds_count(uint32_t addr, uint32_t n)
                            __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// Cache policy of a buffer store: non-temporal (streamed past the caches).
+constexpr int kStoreNT = 2;
+
 // One code row: the next image row arrives in `raw` and becomes `b` (t and m
 // are the two rows above); the row after it moves from `raw2` to `raw`, and
 // the row after that is loaded into `raw2` (clamped to the image's last row).
@@ -284,7 +287,7 @@ __device__ __forceinline__ void lds_count(uint32_t addr, uint32_t n)
 // row ahead, whose next step waited for the previous row's code store too,
 // and faster than giving each row slot its own buffer (no copies, but more
 // live registers: setup values spilled to scratch).
-template <int K, int MODE, bool HIST, bool CODES, bool ALIGNED>
+template <int K, int MODE, bool HIST, bool CODES, bool ALIGNED, bool NT = false>
 __device__ __forceinline__ void step(const ImgView &im, uint32_t *lds_bins, Walk &w, RawRow &raw,
                                      const Row &t, const Row &m, Row &b, RawRow &raw2)
 {
@@ -298,9 +301,9 @@ __device__ __forceinline__ void step(const ImgView &im, uint32_t *lds_bins, Walk
         // pixels 0-3 and 4-7 in column order; dword stores at any byte offset
         // (the target allows unaligned access)
         __builtin_amdgcn_raw_buffer_store_b32(__builtin_amdgcn_perm(q1, q0, 0x05040100u), im.crsrc,
-                                              (int)w.coff, 0, 0);
+                                              (int)w.coff, 0, NT ? kStoreNT : 0);
         __builtin_amdgcn_raw_buffer_store_b32(__builtin_amdgcn_perm(q1, q0, 0x07060302u), im.crsrc,
-                                              (int)(w.coff + 4), 0, 0);
+                                              (int)(w.coff + 4), 0, NT ? kStoreNT : 0);
         w.coff += (uint32_t)im.Wc;
     }
     if constexpr (HIST) {
@@ -325,7 +328,7 @@ __device__ __forceinline__ void step(const ImgView &im, uint32_t *lds_bins, Walk
 // and the tail steps any lane needs, so it takes max(n) steps over its lanes
 // when they all run the loop equally often: n / 3 times with a tail of up to
 // 2, (n - 1) / 3 times with a tail of up to 3.
-template <int K, int MODE, bool HIST, bool CODES, bool ALIGNED>
+template <int K, int MODE, bool HIST, bool CODES, bool ALIGNED, bool NT = false>
 __device__ __forceinline__ void walk_rows(const ImgView &im, uint32_t *lds_bins, Walk &w, int32_t n,
                                           int32_t tail)
 {
@@ -344,21 +347,21 @@ __device__ __forceinline__ void walk_rows(const ImgView &im, uint32_t *lds_bins,
     // the three rows rotate through A, B, C so no registers are copied
     // between rows
     for (; n > tail; n -= 3) {
-        step<K, MODE, HIST, CODES, ALIGNED>(im, lds_bins, w, raw, A, B, C, raw2);
-        step<K, MODE, HIST, CODES, ALIGNED>(im, lds_bins, w, raw, B, C, A, raw2);
-        step<K, MODE, HIST, CODES, ALIGNED>(im, lds_bins, w, raw, C, A, B, raw2);
+        step<K, MODE, HIST, CODES, ALIGNED, NT>(im, lds_bins, w, raw, A, B, C, raw2);
+        step<K, MODE, HIST, CODES, ALIGNED, NT>(im, lds_bins, w, raw, B, C, A, raw2);
+        step<K, MODE, HIST, CODES, ALIGNED, NT>(im, lds_bins, w, raw, C, A, B, raw2);
     }
     if (n >= 1)
-        step<K, MODE, HIST, CODES, ALIGNED>(im, lds_bins, w, raw, A, B, C, raw2);
+        step<K, MODE, HIST, CODES, ALIGNED, NT>(im, lds_bins, w, raw, A, B, C, raw2);
     if (n >= 2)
-        step<K, MODE, HIST, CODES, ALIGNED>(im, lds_bins, w, raw, B, C, A, raw2);
+        step<K, MODE, HIST, CODES, ALIGNED, NT>(im, lds_bins, w, raw, B, C, A, raw2);
     if (n >= 3)
-        step<K, MODE, HIST, CODES, ALIGNED>(im, lds_bins, w, raw, C, A, B, raw2);
+        step<K, MODE, HIST, CODES, ALIGNED, NT>(im, lds_bins, w, raw, C, A, B, raw2);
 }
 
 // Run code rows [r0, r1) of the column group `c`; with HIST they all lie in
 // the cell row whose histograms start at LDS byte `rowb`.
-template <int K, int MODE, bool HIST, bool CODES>
+template <int K, int MODE, bool HIST, bool CODES, bool NT = false>
 __device__ __forceinline__ void run_task(const ImgView &im, uint32_t *lds_bins, uint32_t rowb,
                                          const Cols &c, int32_t r0, int32_t r1)
 {
@@ -380,9 +383,9 @@ __device__ __forceinline__ void run_task(const ImgView &im, uint32_t *lds_bins, 
     // every row of every lane of the wave starts 4-aligned: the walk without
     // realignment (typical: all column groups but an image's last one)
     if (__all(((w.off | im.stride) & 3u) == 0))
-        walk_rows<K, MODE, HIST, CODES, true>(im, lds_bins, w, n, tail);
+        walk_rows<K, MODE, HIST, CODES, true, NT>(im, lds_bins, w, n, tail);
     else
-        walk_rows<K, MODE, HIST, CODES, false>(im, lds_bins, w, n, tail);
+        walk_rows<K, MODE, HIST, CODES, false, NT>(im, lds_bins, w, n, tail);
 }
 
 // Code rows [r0, r1) of a code map narrower than 8 columns: one lane, the
@@ -454,7 +457,11 @@ __device__ void run_task_narrow(const ImgView &im, uint32_t *lds_bins, uint32_t 
 // and two lanes adding into one LDS word are serialised.  The flush adds the
 // copies.  (A compile-time count: with one copy the code is that of a single
 // set of histograms, whose per-item work small items feel.)
-template <int K, int MODE, bool CODES, int COPIES = 1>
+//
+// NT: code and histogram stores are non-temporal, for work whose output is
+// mostly histograms (small windows): they stream past the caches instead of
+// displacing the image rows that neighbouring lanes still read.
+template <int K, int MODE, bool CODES, int COPIES = 1, bool NT = false>
 __device__ __forceinline__ void fused_item(const ImgView &im, uint32_t *lds, const Geom &geo,
                                            int32_t cy0, int32_t cy1, int32_t cx0, int32_t cx1,
                                            int32_t r0, int32_t r1, uint32_t *hist,
@@ -535,7 +542,8 @@ __device__ __forceinline__ void fused_item(const ImgView &im, uint32_t *lds, con
                     const int32_t a0 = a + (int32_t)(qs + udiv_small(rs, nb));
                     const int32_t a1 = a + (int32_t)(qs + qn + udiv_small(rs + rn, nb));
                     if (a1 > a0)
-                        run_task<K, MODE, true, CODES>(im, bins, (cy - cy0) * row_bytes, c, a0, a1);
+                        run_task<K, MODE, true, CODES, NT>(im, bins, (cy - cy0) * row_bytes, c, a0,
+                                                           a1);
                 }
             }
         } else {
@@ -545,7 +553,7 @@ __device__ __forceinline__ void fused_item(const ImgView &im, uint32_t *lds, con
                     b = min(r1, geom_row_start(geo, cy + 1, im.Hc));
                 }
                 for (int32_t g = tid; g < ngroups; g += nthreads)
-                    run_task<K, MODE, true, CODES>(
+                    run_task<K, MODE, true, CODES, NT>(
                         im, bins, (cy - cy0) * row_bytes,
                         group_cols<true>(geo, g, c_lo, c_hi, cx0, ncell, im.Wc), a, b);
             }
@@ -563,8 +571,13 @@ __device__ __forceinline__ void fused_item(const ImgView &im, uint32_t *lds, con
             const u32x4 *src1 = reinterpret_cast<const u32x4 *>(lds + copy_words + r * row_words);
             global_u32x4 *dst =
                 (global_u32x4 *)(hist + ((int64_t)(cy0 + r) * geo.nx + cx0) * 256);
-            for (int32_t i = tid; i < ncell * 64; i += nthreads)
-                dst[i] = COPIES > 1 ? src[i] + src1[i] : src[i];
+            for (int32_t i = tid; i < ncell * 64; i += nthreads) {
+                const u32x4 v = COPIES > 1 ? src[i] + src1[i] : src[i];
+                if constexpr (NT)
+                    __builtin_nontemporal_store(v, &dst[i]);
+                else
+                    dst[i] = v;
+            }
         }
         return;
     }

@@ -319,26 +319,30 @@ def test_plan_layout_histogram_copies(lib):
     """Plans take two LDS copies of the histograms only when the kernel keeps
     as many workgroups per CU with them: the 490x640 frames with 7x6 cells on
     256 threads and 2 cell rows per item (2 x 14 KB) do; 4 cell rows per item
-    (2 x 28 KB would halve the workgroups) and window plans do not."""
+    (2 x 28 KB would halve the workgroups) and window plans do not.  Only
+    window plans of small windows store non-temporally."""
     Hs, Ws = [490] * 4, [640] * 4
     b = Batch(Hs, Ws, synth.KIND_BLUR_RECTS, 11, (7, 6), row_align=4)
     row = (6 + 1) * 1024   # one cell row: 6 cells and the discard cell
     for cpi, copies in ((2, 2), (4, 1)):
         plan = _plan(lib, b, 3, (7, 6), dict(block_threads=256,
                                               classes=[dict(cell_rows_per_item=cpi)]))
-        th, lds, cp = plan.layout()
+        th, lds, cp, nt = plan.layout()
         # two copies: the second starts 64 bytes (16 banks) past the first's end
         slot = cpi * row + (64 if copies == 2 else 0)
-        assert (th, cp) == (256, copies) and lds == copies * slot + 16, (cpi, th, lds, cp)
+        assert (th, cp, nt) == (256, copies, 0) and lds == copies * slot + 16, (cpi, th, lds, cp)
         plan.run()
         torch.cuda.synchronize()
         for j in range(len(Hs)):
             b.check(j, 3, (7, 6))
         plan.close()
-    win = lib.BatchPlan(4, 4 * 490 * 640, 3, 20, 20, dict(block_threads=256), windows=True,
-                        max_width=640)
-    assert win.layout()[2] == 1
-    win.close()
+    # window plans: one copy; non-temporal stores for windows of at most
+    # 1024 pixels
+    for (wy, wx), nt in (((20, 20), 1), ((32, 32), 1), ((33, 32), 0), ((50, 50), 0)):
+        win = lib.BatchPlan(4, 4 * 490 * 640, 3, wy, wx, dict(block_threads=256), windows=True,
+                            max_width=640)
+        assert win.layout()[2:] == (1, nt), (wy, wx, win.layout())
+        win.close()
 
 
 def _stripes(H, W, period, seed):

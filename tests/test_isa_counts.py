@@ -44,7 +44,11 @@ def main_loop_valu(asm, k, mode, copies=1):
                   re.M)
     assert m, "batch_kernel<%d, %d, %d> not found" % (k, mode, copies)
     i = m.start()
-    body = asm[i:asm.index(".Lfunc_end", i)]
+    return _loop_valu(asm[i:asm.index(".Lfunc_end", i)])
+
+
+def _loop_valu(body):
+    """Fewest VALU instructions of the main row loops of one function."""
     blocks = _blocks(body)
     counts = []
     for lab, com, _ in blocks:
@@ -55,18 +59,31 @@ def main_loop_valu(asm, k, mode, copies=1):
         ins = [x for b in members for x in b[2]]
         if sum(x.startswith("ds_") for x in ins) == 24:
             counts.append(sum(x.startswith("v_") for x in ins))
-    assert counts, "no main row loop found in batch_kernel<%d, %d>" % (k, mode)
+    assert counts, "no main row loop found"
     return min(counts)
 
 
-@pytest.mark.skipif(not os.path.exists(build.HIPCC), reason="hipcc not installed")
-def test_valu_per_row_step_matches_generated_code(tmp_path):
+def _function(asm, prefix):
+    """The assembly of the first function whose symbol starts with `prefix`."""
+    m = re.search(r"^(%s\w*):" % prefix, asm, re.M)
+    assert m, prefix
+    return asm[m.start():asm.index(".Lfunc_end", m.start())]
+
+
+@pytest.fixture(scope="module")
+def batch_asm(tmp_path_factory):
+    if not os.path.exists(build.HIPCC):
+        pytest.skip("hipcc not installed")
     src = os.path.join(build.CSRC, "ldp_batch.hip")
-    out = str(tmp_path / "batch.s")
+    out = str(tmp_path_factory.mktemp("isa") / "batch.s")
     cmd = [build.HIPCC] + build.COMMON + ["--cuda-device-only", "-S", src, "-o", out]
     p = subprocess.run(cmd, capture_output=True, text=True)
     assert p.returncode == 0, p.stderr[-2000:]
-    asm = open(out).read()
+    return open(out).read()
+
+
+def test_valu_per_row_step_matches_generated_code(batch_asm):
+    asm = batch_asm
     # the kernels with one and with two LDS copies of the histograms share
     # the row loop
     for copies in (1, 2):
@@ -76,3 +93,17 @@ def test_valu_per_row_step_matches_generated_code(tmp_path):
                 n = main_loop_valu(asm, k, mode, copies)
                 assert table[k] * 3 == pytest.approx(n), (mode, k, copies, n)
         assert bench.VALU_PER_ROW_STEP_LBP * 3 == pytest.approx(main_loop_valu(asm, 1, 3, copies))
+
+
+def test_non_temporal_stores_only_in_the_nt_kernel(batch_asm):
+    """batch_kernel_nt streams its code stores and its 16-byte histogram
+    flush past the caches (the `nt` cache-policy bit); the cell-grid kernels
+    (one and two histogram copies) store through them."""
+    nt = _function(batch_asm, "_ZN3ldp15batch_kernel_ntILi3ELi0EEEv")
+    assert re.search(r"buffer_store_dword v\d+, v\d+, s\[\d+:\d+\], 0 offen.* nt", nt)
+    assert re.search(r"global_store_dwordx4 .* nt", nt)
+    for copies in (1, 2):
+        plain = _function(batch_asm, "_ZN3ldp12batch_kernelILi3ELi0ELi%dEEEv" % copies)
+        assert "buffer_store_dword" in plain and not re.search(r"_store_\w+ .* nt\b", plain)
+    # the same row loop, with another cache policy on its stores
+    assert _loop_valu(nt) == main_loop_valu(batch_asm, 3, 0, 1)
