@@ -24,3 +24,14 @@ def test_one_hip_runtime_when_binding_loads_first():
     assert p.returncode == 0, p.stderr[-2000:]
     lines = p.stdout.strip().splitlines()
     assert lines[0] == "1", lines
+
+
+@pytest.mark.parametrize("n", [0, 2, 8])
+def test_bench_refuses_other_gpu_counts(n):
+    """bench.py measures one GPU: any other --gpus value exits with status 2
+    and says why, before it touches a device."""
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    p = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", str(n)],
+                       capture_output=True, text=True, timeout=120)
+    assert p.returncode == 2, (p.returncode, p.stderr[-500:])
+    assert "one GPU" in p.stderr and p.stdout == ""
