@@ -415,9 +415,11 @@ def now():
 class Server:
     """Continuous-batching request server (ldp_server_*).
 
-    submit() takes HOST numpy buffers (page-locked ones, e.g. views of
-    torch.empty(..., pin_memory=True), give asynchronous copies); they are
-    kept alive here until the request completes.
+    submit() takes HOST numpy buffers; they are kept alive here until the
+    request completes.  Page-locked ones (e.g. views of torch.empty(...,
+    pin_memory=True)) are read and written by the kernel in place; pageable
+    ones go through the server's page-locked mirror of its memory pool
+    (copied in before the batch's launch and out once it has run).
     """
 
     def __init__(self, pool_bytes, max_inflight, max_batch, depth, k, cells_y, cells_x,
