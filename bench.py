@@ -448,11 +448,15 @@ def _drive(binding, srv, sched, imgs, outs, pool_images):
     """Open-loop driver: submit request i at scheduled host time sched[i]
     (image i % pool_images), collect completions; returns per-request
     latency (results on the host - scheduled arrival), admission delay, batch
-    size, statuses, the pixels submitted and the last completion time."""
+    size, statuses, the pixels submitted, the last completion time, and the
+    latency's other two parts: submission lag (submitted - scheduled) and
+    service time (results on the host - admitted)."""
     n = len(sched)
     nout = len(outs)
     lat = np.zeros(n)
     adm = np.zeros(n)
+    lag = np.zeros(n)
+    svc = np.zeros(n)
     sizes = np.zeros(n)
     status = np.zeros(n, dtype=np.int64)
     i = done = 0
@@ -472,11 +476,13 @@ def _drive(binding, srv, sched, imgs, outs, pool_images):
             q = c["id"] - first
             lat[q] = c["t_done"] - sched[q]
             adm[q] = c["t_admit"] - c["t_submit"]
+            lag[q] = c["t_submit"] - sched[q]
+            svc[q] = c["t_done"] - c["t_admit"]
             sizes[q] = c["batch_size"]
             status[q] = c["status"]
             done += 1
             last_done = c["t_done"]
-    return lat, adm, sizes, status, px, last_done
+    return lat, adm, sizes, status, px, last_done, lag, svc
 
 
 def serve_bench(binding, synth, torch, rates, n_req, k=3, cells=(7, 6), pool_images=256,
@@ -522,8 +528,8 @@ def serve_bench(binding, synth, torch, rates, n_req, k=3, cells=(7, 6), pool_ima
             _drive(binding, srv, binding.now() + 0.01 + arr[:nw], imgs, pc["outs"], pool_images)
             st0 = srv.stats()
             t0 = binding.now() + 0.02
-            lat, adm, sizes, status, px, last_done = _drive(binding, srv, t0 + arr, imgs,
-                                                            pc["outs"], pool_images)
+            lat, adm, sizes, status, px, last_done, lag, svc = _drive(
+                binding, srv, t0 + arr, imgs, pc["outs"], pool_images)
             st = srv.stats()
             srv.close()
             span = last_done - t0
@@ -533,6 +539,11 @@ def serve_bench(binding, synth, torch, rates, n_req, k=3, cells=(7, 6), pool_ima
                          "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
                          "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
                          "admission_p99_ms": round(float(np.percentile(adm, 99)) * 1e3, 3),
+                         # the p50 latency's parts: the driver's submission lag,
+                         # admission, and launch + kernel + completion
+                         "submit_lag_p50_ms": round(float(np.percentile(lag, 50)) * 1e3, 3),
+                         "admission_p50_ms": round(float(np.percentile(adm, 50)) * 1e3, 3),
+                         "service_p50_ms": round(float(np.percentile(svc, 50)) * 1e3, 3),
                          "memory_waits": int(st["memory_waits"] - st0["memory_waits"]),
                          "peak_pool_bytes": int(st["peak_pool_bytes"]),
                          "pool_bytes": int(pc["pool"]),

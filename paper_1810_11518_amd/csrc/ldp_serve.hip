@@ -23,6 +23,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -136,6 +137,7 @@ struct ldp_server {
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::deque<Req *> pending;
+    std::atomic<uint64_t> n_submitted{0};  // read by the dispatcher without the lock
     std::vector<Batch> inflight;
     std::deque<ldp_completion> done;
     int inflight_reqs = 0;
@@ -155,6 +157,11 @@ namespace {
 // so each image is spread over many short lane tasks (one cell row per work
 // item, row bands of >= 4 rows, large workgroups) rather than few long ones.
 const ldp_tune kServeTune = {LDP_SERVE_THREADS, 0, 1, 0, {{INT64_MAX, 1, 4}}};
+
+// The dispatcher spins (instead of sleeping) for this long after its last
+// admission, launch or retirement, polling in slices of kSpinPollSeconds.
+constexpr double kSpinSeconds = 200e-6;
+constexpr double kSpinPollSeconds = 2e-6;
 
 // Pools up to this size get their page-locked mirror at server creation.
 constexpr int64_t kEagerMirror = int64_t(256) << 20;
@@ -291,6 +298,7 @@ void dispatcher(ldp_server *s)
     if (!s->cfg.dry_run)
         (void)hipSetDevice(s->device);
     std::unique_lock<std::mutex> lk(s->mu);
+    double t_work = now_s();  // the last admission, launch or retirement
     for (;;) {
         bool progressed = false;
         // retire finished batches: copy staged results out (without the lock:
@@ -388,13 +396,27 @@ void dispatcher(ldp_server *s)
         s->st.waiting = (int32_t)s->pending.size();
         if (s->stop && s->pending.empty() && s->inflight.empty())
             break;
-        if (!progressed) {
-            // idle: wait for a submission; batches in flight: poll their
-            // events every 5 us, and wake at once for a submission
-            if (s->inflight.empty())
-                s->cv_work.wait_for(lk, std::chrono::milliseconds(2));
-            else
-                s->cv_work.wait_for(lk, std::chrono::microseconds(5));
+        const double tnow = now_s();
+        if (progressed) {
+            t_work = tnow;
+        } else if (!s->cfg.dry_run && tnow - t_work < kSpinSeconds) {
+            // Busy within the last kSpinSeconds: spin for one short poll
+            // interval with the lock released instead of sleeping, so a new
+            // submission is admitted at once (a sleeping thread takes ~5-10
+            // us to wake) and batches in flight are polled every ~2 us.
+            const uint64_t seen = s->n_submitted.load(std::memory_order_acquire);
+            lk.unlock();
+            while (now_s() - tnow < kSpinPollSeconds &&
+                   s->n_submitted.load(std::memory_order_acquire) == seen)
+                __builtin_ia32_pause();
+            lk.lock();
+        } else if (s->inflight.empty()) {
+            // idle: wait for a submission
+            s->cv_work.wait_for(lk, std::chrono::milliseconds(2));
+        } else {
+            // batches in flight: poll their events every 5 us, and wake at
+            // once for a submission
+            s->cv_work.wait_for(lk, std::chrono::microseconds(5));
         }
     }
 }
@@ -566,6 +588,7 @@ int ldp_server_submit(ldp_server *s, const uint8_t *img, int32_t H, int32_t W, i
     *id = r->id;
     s->pending.push_back(r);
     s->st.submitted += 1;
+    s->n_submitted.fetch_add(1, std::memory_order_release);
     s->cv_work.notify_one();
     return LDP_OK;
 }
